@@ -1,0 +1,448 @@
+"""Pins of the FP64 oracle to facts that do not come from the oracle itself.
+
+Each test checks the oracle against something the paper or mathematics fixes: closed-form value
+functions, a brute-force dynamic-programming solve (eq. (8)), polynomial exactness and order of
+accuracy of the textbook schemes, the theorems of Sec. III, the problem's symmetries, and
+explicit lattice searches for the Hamiltonian's max-min (eq. (6)).  A plausible mistake anywhere
+in the oracle -- a dropped WENO term, a wrong dissipation sign, a swapped max/min, a wrong RK3
+coefficient, a transposed stencil -- fails at least one of these.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.interpolate import RegularGridInterpolator
+
+from paper_1903_07715_amd import workloads as W
+
+AVOID, REACH = 0, 1
+
+
+# ---------------------------------------------------------------------------------------------
+# Derivative approximations
+# ---------------------------------------------------------------------------------------------
+
+def _line_grid(n, lo=-1.0, hi=1.0, periodic=False):
+    # second dimension of 3 nodes only so the grid is 2-D; derivatives are taken along dim 0
+    return W.Grid((n, 3), (lo, 0.0), (hi, 1.0), (periodic, False))
+
+
+def test_upwind_and_weno_exact_on_linear_data_including_boundaries(orc):
+    """Linear data: both one-sided differences and WENO5 are exact at every node, including
+    the boundary nodes, because linear ghost extrapolation continues a linear function."""
+    g = _line_grid(17)
+    x = g.mesh()[0] + 0.0 * g.mesh()[1]
+    V = 0.7 - 2.5 * x
+    for spatial in (orc.UPWIND1, orc.WENO5):
+        for j in range(17):
+            dm, dp = orc.derivatives(g, V, j * 3 + 1, 0, spatial)
+            assert abs(dm + 2.5) < 1e-12 and abs(dp + 2.5) < 1e-12
+
+
+def test_weno5_exact_on_cubics_in_the_interior(orc):
+    """Each WENO5 candidate is a third-order interpolant, exact for cubics, and the weights sum
+    to one, so D- and D+ reproduce the derivative of any cubic (Osher and Fedkiw, Sec. 3.4)."""
+    rng = np.random.default_rng(1)
+    g = _line_grid(21)
+    x = g.mesh()[0] + 0.0 * g.mesh()[1]
+    for _ in range(5):
+        c = rng.normal(size=4)
+        V = c[0] + c[1] * x + c[2] * x ** 2 + c[3] * x ** 3
+        xs = g.axis(0)
+        dV = c[1] + 2 * c[2] * xs + 3 * c[3] * xs ** 2
+        for j in range(3, 21 - 3):
+            dm, dp = orc.derivatives(g, V, j * 3, 0, orc.WENO5)
+            assert abs(dm - dV[j]) < 1e-9 * (1 + abs(dV[j]))
+            assert abs(dp - dV[j]) < 1e-9 * (1 + abs(dV[j]))
+
+
+def test_weno5_fifth_order_on_smooth_periodic_data(orc):
+    """On smooth data the weights approach (0.1, 0.6, 0.3) and the scheme is fifth order."""
+    errs = []
+    for n in (64, 128):
+        g = W.Grid((n, 4), (0.0, 0.0), (2 * math.pi, 1.0), (True, True))
+        X = g.mesh()[0] + 0.0 * g.mesh()[1]
+        V = np.sin(X) + 0.3 * np.cos(2 * X)
+        exact = np.cos(g.axis(0)) - 0.6 * np.sin(2 * g.axis(0))
+        e = 0.0
+        for j in range(n):
+            dm, dp = orc.derivatives(g, V, j * 4, 0, orc.WENO5)
+            e = max(e, abs(dm - exact[j]), abs(dp - exact[j]))
+        errs.append(e)
+    assert errs[0] / errs[1] > 25.0  # 2^5 = 32 in the asymptotic regime
+
+
+def test_weno5_matches_textbook_linear_scheme_on_smooth_data(orc):
+    """With equal smoothness the weights are the ideal ones and WENO5 equals the fifth-order
+    upwind-biased formula (2 v1 - 13 v2 + 47 v3 + 27 v4 - 3 v5) / 60."""
+    for v in ([1.0, 2.0, 3.0, 4.0, 5.0], [0.3, 0.3, 0.3, 0.3, 0.3]):
+        lin = (2 * v[0] - 13 * v[1] + 47 * v[2] + 27 * v[3] - 3 * v[4]) / 60.0
+        assert abs(orc.weno5(*v) - lin) < 1e-14
+    h = 1e-3
+    v = [math.cos(h * k) for k in range(5)]
+    lin = (2 * v[0] - 13 * v[1] + 47 * v[2] + 27 * v[3] - 3 * v[4]) / 60.0
+    assert abs(orc.weno5(*v) - lin) < 1e-9
+
+
+def test_weno5_avoids_a_kink(orc):
+    """ENO property: next to a kink the weight of any stencil that crosses it vanishes, so the
+    one-sided derivative is taken from the smooth side (error far below the linear scheme's)."""
+    g = _line_grid(41)
+    x = g.mesh()[0] + 0.0 * g.mesh()[1]
+    x0 = 0.013
+    V = np.abs(x - x0)
+    xs = g.axis(0)
+    j = int(np.searchsorted(xs, x0)) + 1  # second node right of the kink
+    dm, _ = orc.derivatives(g, V, j * 3, 0, orc.WENO5)
+    assert abs(dm - 1.0) < 2e-3
+    dx = xs[1] - xs[0]
+    D = [(abs(xs[j + o] - x0) - abs(xs[j + o - 1] - x0)) / dx for o in range(-2, 3)]
+    lin = (2 * D[0] - 13 * D[1] + 47 * D[2] + 27 * D[3] - 3 * D[4]) / 60.0
+    assert abs(lin - 1.0) > 20 * abs(dm - 1.0)
+
+
+# ---------------------------------------------------------------------------------------------
+# Hamiltonian, eq. (6): lattice search over (u, d)
+# ---------------------------------------------------------------------------------------------
+
+def _flow_np(dyn, x, u, d):
+    """The model equations, written from their definitions (Sec. II-A eq. (2) and the benchmark
+    models), evaluated on arrays of inputs."""
+    q = dyn.params
+    if dyn.id == W.DYN_DOUBLE_INTEGRATOR:
+        return [x[1] + d[0], q[1] * u[0]]
+    if dyn.id == W.DYN_DUBINS3:
+        return [q[0] * math.cos(x[2]) + d[0], q[0] * math.sin(x[2]) + d[1], u[0]]
+    if dyn.id == W.DYN_UNICYCLE4:
+        return [x[3] * math.cos(x[2]) + d[0], x[3] * math.sin(x[2]) + d[1], u[0], u[1]]
+    g, m = q[0], q[1]
+    return [x[3], x[4], x[5], g * np.tan(u[0]) + d[0], -g * np.tan(u[1]) + d[1], u[2] / m - g + d[2]]
+
+
+def _lattices(dyn, k=7):
+    q = dyn.params
+    lin = lambda a, b: np.linspace(a, b, k)
+    if dyn.id == W.DYN_DOUBLE_INTEGRATOR:
+        U = [lin(-q[0], q[0])]
+        D = [lin(-q[2], q[2])]
+    elif dyn.id == W.DYN_DUBINS3:
+        U = [lin(-q[1], q[1])]
+        D = [lin(-q[2], q[2]), lin(-q[3], q[3])]
+    elif dyn.id == W.DYN_UNICYCLE4:
+        U = [lin(-q[0], q[0]), lin(-q[1], q[1])]
+        if q[3] == 0.0:  # ball: polar lattice of the disk
+            r = np.linspace(0, q[2], 9)
+            a = np.linspace(0, 2 * math.pi, 721)
+            R, A = np.meshgrid(r, a)
+            D = [(R * np.cos(A)).ravel(), (R * np.sin(A)).ravel()]
+            return np.stack(np.meshgrid(*U, indexing="ij"), -1).reshape(-1, 2), np.stack(D, -1)
+        D = [lin(-q[2], q[2]), lin(-q[2], q[2])]
+    else:
+        U = [lin(-q[3], q[3]), lin(-q[2], q[2]), lin(q[4], q[5])]
+        D = [lin(-q[6], q[6]), lin(-q[7], q[7]), lin(-q[8], q[8])]
+    Ug = np.stack(np.meshgrid(*U, indexing="ij"), -1).reshape(-1, len(U))
+    Dg = np.stack(np.meshgrid(*D, indexing="ij"), -1).reshape(-1, len(D))
+    return Ug, Dg
+
+
+@pytest.mark.parametrize("dyn", [W.double_integrator(1.0, 0.8, 0.3), W.dubins3(1.0, 1.5, 0.1, 0.2),
+                                 W.unicycle4(1.0, 0.5, 0.1), W.unicycle4(1.0, 0.5, 0.1, box=True),
+                                 W.quad6(1.2, (0.5, 0.3, 0.4))])
+@pytest.mark.parametrize("game", [AVOID, REACH])
+def test_hamiltonian_equals_lattice_max_min(orc, dyn, game):
+    rng = np.random.default_rng(7)
+    Ug, Dg = _lattices(dyn)
+    for _ in range(6):
+        x = rng.uniform(-2, 2, size=dyn.ndim)
+        if dyn.id == W.DYN_UNICYCLE4:
+            x[3] = rng.uniform(0, 2)
+        p = rng.normal(size=dyn.ndim)
+        H, alpha = orc.hamiltonian(dyn, x, p, game)
+        vals = np.empty((len(Ug), len(Dg)))
+        amax = np.zeros(dyn.ndim)
+        for a, u in enumerate(Ug):
+            f = _flow_np(dyn, x, u, Dg.T)
+            vals[a] = sum(pi * np.asarray(fi) for pi, fi in zip(p, f))
+            amax = np.maximum(amax, [np.max(np.abs(np.broadcast_to(fi, (len(Dg),)))) for fi in f])
+        Hl = vals.min(axis=1).max() if game == AVOID else vals.max(axis=1).min()
+        tol = 1e-4 if (dyn.id == W.DYN_UNICYCLE4 and dyn.params[3] == 0.0) else 1e-12
+        assert abs(H - Hl) < tol * (1 + abs(Hl))
+        assert np.allclose(alpha, amax, rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------------------------
+# Closed-form value functions
+# ---------------------------------------------------------------------------------------------
+
+def _strip_vstar(P, Vv, D=0.0, b=1.0):
+    """Running example (Sec. II-A/B): unsafe strip |p| <= 2, p' = v + d, v' = b u, |u| <= 1.
+    For p >= 0 the best the control can do is brake; the worst disturbance pushes toward the
+    strip, so the closest approach is p - max(0, D - v)^2 / (2b); crossing p = 0 means the
+    distance reached zero.  V* = max(closest approach, 0) - 2, and V*(p, v) = V*(-p, -v)."""
+    def half(p, v):
+        return np.maximum(p - np.maximum(0.0, D - v) ** 2 / (2 * b), 0.0) - 2.0
+    return np.where(P >= 0, half(P, Vv), half(-P, -Vv))
+
+
+def _strip_errors(orc, n, spatial, temporal, cfl, max_iter):
+    pr = W.di_strip_problem(n, spatial=spatial, temporal=temporal, cfl=cfl)
+    V, info = orc.solve(pr.grid, pr.dyn, pr.l, max_iter=max_iter, **orc.problem_opts(pr))
+    P, Vv = np.meshgrid(pr.grid.axis(0), pr.grid.axis(1), indexing="ij")
+    Vs = _strip_vstar(P, Vv)
+    dx = pr.grid.spacing(0)
+    # away from the domain edge and from the kinks of V* (p = 0 and the plateau boundary)
+    q = np.where(P >= 0, P - np.maximum(0.0, -Vv) ** 2 / 2, -P - np.maximum(0.0, Vv) ** 2 / 2)
+    mask = (np.abs(Vv) <= 3.0) & (np.abs(P) <= 4.0) & (np.abs(q) > 4 * dx) & (np.abs(P) > 4 * dx)
+    err = np.abs(V - Vs)
+    return err[mask].max(), err[mask].mean(), info
+
+
+def test_closed_form_running_example_upwind(orc):
+    e41 = _strip_errors(orc, 41, orc.UPWIND1, orc.EULER, 0.8, 5000)
+    e81 = _strip_errors(orc, 81, orc.UPWIND1, orc.EULER, 0.8, 5000)
+    assert e41[2]["converged"] == 1 and e81[2]["converged"] == 1
+    assert e81[0] < 0.3 and e81[1] < 0.025
+    assert e41[1] / e81[1] > 1.5  # first order: the mean error roughly halves with dx
+
+
+def test_closed_form_running_example_weno(orc):
+    # WENO5 does not settle below 1e-6 here (a small limit cycle at the v = +-5 edge rows),
+    # so it is compared after a fixed number of steps, long after the interior has converged.
+    e41 = _strip_errors(orc, 41, orc.WENO5, orc.RK3, 0.5, 600)
+    e81 = _strip_errors(orc, 81, orc.WENO5, orc.RK3, 0.5, 1200)
+    assert e81[0] < 0.05 and e81[1] < 0.004
+    assert e41[1] / e81[1] > 1.5
+
+
+def _tstar(x1, x2):
+    """Minimum time to the origin for x1' = x2, x2' = u, |u| <= 1 (bang-bang, one switch)."""
+    s = x1 + x2 * np.abs(x2) / 2
+    a = x2 + 2 * np.sqrt(np.maximum(x1 + x2 ** 2 / 2, 0))
+    b = -x2 + 2 * np.sqrt(np.maximum(-x1 + x2 ** 2 / 2, 0))
+    return np.where(s > 0, a, np.where(s < 0, b, np.abs(x2)))
+
+
+@pytest.mark.parametrize("T", [0.5, 1.0, 1.5])
+def test_closed_form_minimum_time_reach_set(orc, T):
+    """Reach game (control minimises): {V(., T) <= 0} is the set that can reach a small box
+    at the origin within T, i.e. {T* <= T} up to the box size and the grid resolution."""
+    g = W.Grid((101, 101), (-2, -2), (2, 2))
+    l = W.box_sdf(g, (0, 0), (0.05, 0.05))
+    V, info = orc.solve(g, W.double_integrator(1.0, 1.0, 0.0), l, spatial=orc.WENO5, temporal=orc.RK3,
+                        cfl=0.5, tol=1e-300, t_max=T, game=REACH)
+    assert info["converged"] == 2 and abs(info["t"] - T) < 1e-9
+    X1, X2 = np.meshgrid(g.axis(0), g.axis(1), indexing="ij")
+    Ts = _tstar(X1, X2)
+    inside = V <= 0
+    wrong = inside != (Ts <= T)
+    assert not np.any(wrong & (np.abs(Ts - T) > 0.4))
+    assert inside.sum() > 4 * (l <= 0).sum()  # the set really grew from the target
+
+
+def test_closed_form_dubins_ray_distance(orc):
+    """No control, no disturbance: the car drives straight on, so V* is the closest approach of
+    the ray to the disk: |(x,y)| - R when moving away, else |x sin th - y cos th| - R."""
+    pr = W.dubins_problem(31, ubar=0.0, dbar=0.0)
+    V, info = orc.solve(pr.grid, pr.dyn, pr.l, max_iter=1000, t_max=15.0, **orc.problem_opts(pr))
+    X, Y, TH = pr.grid.mesh()
+    a = X * np.cos(TH) + Y * np.sin(TH)
+    perp = X * np.sin(TH) - Y * np.cos(TH)
+    ex = np.broadcast_to(np.where(a >= 0, np.sqrt(X ** 2 + Y ** 2) - 1, np.abs(perp) - 1), pr.grid.shape)
+    dx = pr.grid.spacing(0)
+    mask = np.broadcast_to((np.abs(a) > 3 * dx) & (np.abs(perp) > 3 * dx), pr.grid.shape)
+    err = np.abs(V - ex)
+    assert err[mask].max() < 0.08
+    assert err.mean() < 0.01
+
+
+# ---------------------------------------------------------------------------------------------
+# Brute-force dynamic programming (eq. (8))
+# ---------------------------------------------------------------------------------------------
+
+def _semi_lagrangian(g, ubar, b, dbar, l, h=0.02, k=11):
+    """V(x) = max_u min_d min(l(x), V(x + h f(x,u,d))) on the grid, bilinear interpolation,
+    iterated to a fixed point (eq. (8) with one Euler step of the trajectory)."""
+    ax = (g.axis(0), g.axis(1))
+    X1, X2 = np.meshgrid(*ax, indexing="ij")
+    us, ds = np.linspace(-ubar, ubar, k), np.linspace(-dbar, dbar, k)
+    V = l.copy()
+    for _ in range(5000):
+        f = RegularGridInterpolator(ax, V, bounds_error=False, fill_value=None)
+        best = np.full(V.shape, -np.inf)
+        for u in us:
+            worst = np.full(V.shape, np.inf)
+            for d in ds:
+                y = np.stack([(X1 + h * (X2 + d)).ravel(), (X2 + h * b * u).ravel()], -1)
+                worst = np.minimum(worst, f(y).reshape(V.shape))
+            best = np.maximum(best, worst)
+        Vn = np.minimum(l, best)
+        if np.abs(Vn - V).max() < 1e-10:
+            return Vn
+        V = Vn
+    return V
+
+
+@pytest.mark.parametrize("dbar", [0.0, 0.3])
+def test_brute_force_dynamic_programming(orc, dbar):
+    pr = W.di_box_problem(41, ubar=1.0, dbar=dbar)
+    Vo, info = orc.solve(pr.grid, pr.dyn, pr.l, spatial=orc.UPWIND1, temporal=orc.EULER, cfl=0.8, tol=1e-9)
+    Vs = _semi_lagrangian(pr.grid, 1.0, 1.0, dbar, pr.l)
+    assert np.abs(Vo - pr.l).max() > 0.03  # the solve moved V away from l
+    assert np.abs(Vo - Vs).max() < 0.012
+    assert np.abs(Vo - Vs).mean() < 1e-3
+
+
+# ---------------------------------------------------------------------------------------------
+# Theorems of Sec. III and the propositions of the appendix
+# ---------------------------------------------------------------------------------------------
+
+def _periodic_di(n=41, dbar=0.1):
+    g = W.Grid((n, n), (-1, -1), (1, 1), (True, True))
+    return g, W.double_integrator(1.0, 1.0, dbar), W.box_sdf(g, (0, 0), (0.2, 0.2))
+
+
+def test_theorem1_every_iterate_conservative_monotone_scheme(orc):
+    """Theorem 1: V_k(x, t) <= V_l(x, t) for every k and t.  For the monotone scheme
+    (upwind + Lax-Friedrichs + Euler at CFL <= 1, no boundary) this holds exactly for every
+    iterate, since V_k starts at min(k, l) <= l.  k: the unrealistic k of Sec. IV-B, k = 0 of
+    Sec. IV-C and the random circles of Sec. IV-D."""
+    g, dyn, l = _periodic_di()
+    dt = orc.cfl_dt(g, dyn, 0.8)
+    ks = [-l - np.abs(l).max() - 0.1, np.zeros_like(l), W.random_circles_k(g)]
+    for k in ks:
+        Vl, Vk = l.copy(), np.minimum(k, l)
+        for _ in range(150):
+            Vl, _ = orc.step(g, dyn, Vl, l, dt, spatial=orc.UPWIND1, temporal=orc.EULER)
+            Vk, _ = orc.step(g, dyn, Vk, l, dt, spatial=orc.UPWIND1, temporal=orc.EULER)
+            assert (Vk - Vl).max() <= 1e-13
+
+
+def test_theorem1_converged_sets_with_boundaries(orc):
+    """With boundary nodes the converged unsafe set of a warm start contains the standard one."""
+    pr = W.di_box_problem(41, ubar=1.0, dbar=0.1)
+    Vl, _ = orc.solve(pr.grid, pr.dyn, pr.l, **orc.problem_opts(pr))
+    for k in (np.zeros_like(pr.l), W.random_circles_k(pr.grid), -pr.l - np.abs(pr.l).max() - 0.1):
+        Vk, _ = orc.solve(pr.grid, pr.dyn, pr.l, k, max_iter=3000, **orc.problem_opts(pr))
+        assert not np.any((Vl <= 0) & (Vk > 0))
+
+
+def test_sec4_examples_stuck_and_flat(orc):
+    """Sec. IV-B: a k below V* everywhere with wrong gradients stays stuck (the unsafe set is
+    the whole space).  Sec. IV-C: k = 0 stays (nearly) flat at 0 where k < V*, and its unsafe
+    set contains the standard one."""
+    pr = W.di_box_problem(41, ubar=1.0, dbar=0.1)
+    g, dyn, l = pr.grid, pr.dyn, pr.l
+    Vl, _ = orc.solve(g, dyn, l, **orc.problem_opts(pr))
+    k2 = -l - np.abs(l).max() - 0.1
+    V2, _ = orc.solve(g, dyn, l, k2, max_iter=3000, **orc.problem_opts(pr))
+    assert np.all(V2 <= 0)
+    V3, _ = orc.solve(g, dyn, l, np.zeros_like(l), **orc.problem_opts(pr))
+    assert np.all(V3 <= 1e-15) and np.all(V3 <= Vl + 1e-5)
+    assert np.abs(V3[Vl > 0.1]).max() < 1e-3
+
+
+def test_theorem2_and_propositions_exact(orc):
+    """k >= V*_new gives V*_k = V*_new (Theorem 2): disturbance grows (Sec. V-C), control
+    shrinks (Prop. 2, b: 1 -> 0.8) and target grows (Prop. 1, strip 2 -> 2.5)."""
+    q0, q1 = W.di_box_problem(41, dbar=0.0), W.di_box_problem(41, dbar=0.3)
+    V0, _ = orc.solve(q0.grid, q0.dyn, q0.l, **orc.problem_opts(q0))
+    V1, i1 = orc.solve(q1.grid, q1.dyn, q1.l, **orc.problem_opts(q1))
+    Vw, iw = orc.solve(q1.grid, q1.dyn, q1.l, V0, **orc.problem_opts(q1))
+    assert np.abs(V0 - V1).max() > 0.05 and np.abs(Vw - V1).max() < 1e-6
+
+    s0, s1 = W.di_strip_problem(41, b=1.0), W.di_strip_problem(41, b=0.8)
+    S0, _ = orc.solve(s0.grid, s0.dyn, s0.l, **orc.problem_opts(s0))
+    S1, j1 = orc.solve(s1.grid, s1.dyn, s1.l, **orc.problem_opts(s1))
+    Sw, jw = orc.solve(s1.grid, s1.dyn, s1.l, S0, **orc.problem_opts(s1))
+    assert np.abs(S0 - S1).max() > 0.1 and np.abs(Sw - S1).max() < 1e-5
+    assert jw["steps"] < j1["steps"]
+
+    l2 = W.strip_target(s0.grid, 2.5)
+    T2, _ = orc.solve(s0.grid, s0.dyn, l2, **orc.problem_opts(s0))
+    Tw, _ = orc.solve(s0.grid, s0.dyn, l2, S0, **orc.problem_opts(s0))
+    assert np.abs(Tw - T2).max() < 1e-6
+
+
+def test_remark2_bounds_when_control_grows(orc):
+    """Remark 2: warm start from the solution with less control: k <= V_k <= V*_new."""
+    s0, s1 = W.di_strip_problem(41, b=1.0), W.di_strip_problem(41, b=0.8)
+    S0, _ = orc.solve(s0.grid, s0.dyn, s0.l, **orc.problem_opts(s0))
+    S1, _ = orc.solve(s1.grid, s1.dyn, s1.l, **orc.problem_opts(s1))
+    Sr, _ = orc.solve(s0.grid, s0.dyn, s0.l, S1, **orc.problem_opts(s0))
+    assert (S1 - Sr).max() <= 1e-12 and (Sr - S0).max() <= 1e-12
+    assert np.abs(Sr - S0).max() < 1e-4
+
+
+# ---------------------------------------------------------------------------------------------
+# Special cases, symmetry, time-step independence, time order
+# ---------------------------------------------------------------------------------------------
+
+def test_special_cases(orc):
+    pr = W.di_box_problem(41, dbar=0.3)
+    V, info = orc.solve(pr.grid, pr.dyn, pr.l, **orc.problem_opts(pr))
+    Vk, infok = orc.solve(pr.grid, pr.dyn, pr.l, pr.l, **orc.problem_opts(pr))
+    assert np.array_equal(V, Vk) and info["steps"] == infok["steps"]  # k = l is the cold solve
+    Vs, infos = orc.solve(pr.grid, pr.dyn, pr.l, V, **orc.problem_opts(pr))
+    assert infos["steps"] == 1 and infos["converged"] == 1  # k = V* is already converged
+    g = W.Grid((9, 9, 12), (-1, -1, -math.pi), (1, 1, math.pi), (False, False, True))
+    still = W.dubins3(0.0, 0.0, 0.0)  # f = 0 everywhere
+    l = W.disk_sdf(g, (0, 0), 0.5)
+    k = W.random_circles_k(g)
+    Vz, iz = orc.solve(g, still, l, k, spatial=orc.WENO5, temporal=orc.RK3, cfl=0.5, tol=1e-6)
+    assert iz["steps"] == 1 and iz["dt"] == 1.0
+    assert np.abs(Vz - np.minimum(k, l)).max() < 1e-15  # RK3 weights reassemble V up to rounding
+
+
+def test_symmetry(orc):
+    pr = W.di_box_problem(41, dbar=0.2)
+    V, _ = orc.solve(pr.grid, pr.dyn, pr.l, **orc.problem_opts(pr))
+    assert np.abs(V - V[::-1, ::-1]).max() < 1e-12  # (p, v) -> (-p, -v)
+    dp = W.dubins_problem(21)
+    V, _ = orc.solve(dp.grid, dp.dyn, dp.l, max_iter=60, **orc.problem_opts(dp))
+    nt = dp.grid.n[2]
+    Vm = V[:, ::-1, :][:, :, (-np.arange(nt)) % nt]  # (x, y, th) -> (x, -y, -th)
+    assert np.abs(V - Vm).max() < 1e-12
+
+
+def test_fixed_point_independent_of_cfl(orc):
+    """Where V < l the Euler fixed point solves L(V) = 0, which does not involve dt."""
+    pr = W.di_box_problem(41, dbar=0.3)
+    a, ia = orc.solve(pr.grid, pr.dyn, pr.l, spatial=orc.UPWIND1, temporal=orc.EULER, cfl=0.8, tol=1e-10)
+    b, ib = orc.solve(pr.grid, pr.dyn, pr.l, spatial=orc.UPWIND1, temporal=orc.EULER, cfl=0.4, tol=1e-10)
+    assert ib["steps"] > 1.5 * ia["steps"]
+    assert np.abs(a - b).max() < 1e-7
+
+
+def test_rk3_is_third_order_euler_first(orc):
+    """Pure advection (Dubins with no control or disturbance on a fully periodic box, l never
+    binding): the exact solution is the initial field carried along straight lines."""
+    def err(n, temporal):
+        g = W.Grid((n, n, 8), (-math.pi,) * 3, (math.pi,) * 3, (True, True, True))
+        X, Y, TH = g.mesh()
+        k = np.broadcast_to(np.sin(X) * np.cos(Y), g.shape).copy()
+        l = np.full(g.shape, 1e9)
+        V, info = orc.solve(g, W.dubins3(1.0, 0.0, 0.0), l, k, spatial=orc.WENO5, temporal=temporal, cfl=0.5,
+                            tol=1e-300, t_max=1.0)
+        return np.abs(V - np.sin(X + np.cos(TH)) * np.cos(Y + np.sin(TH))).max()
+    r3 = err(16, orc.RK3) / err(32, orc.RK3)
+    r1 = err(16, orc.EULER) / err(32, orc.EULER)
+    assert r3 > 6.0 and 1.6 < r1 < 2.6
+
+
+def test_interval_mode_lands_on_interval_ends(orc):
+    """Sec. IV rule: the change over each dt = 0.01 interval is tested against 1e-3."""
+    pr = W.di_box_problem(41, dbar=0.1)
+    V, info = orc.solve(pr.grid, pr.dyn, pr.l, spatial=orc.UPWIND1, temporal=orc.EULER, cfl=0.8, tol=1e-3,
+                        conv_mode=orc.CONV_INTERVAL, dt_report=0.01)
+    assert info["converged"] == 1 and info["last_delta"] < 1e-3
+    assert abs(info["t"] - 0.01 * info["intervals"]) < 1e-12
+    per = math.ceil(0.01 / info["dt"] - 1e-12)
+    assert info["steps"] == per * info["intervals"]
+
+
+def test_nonfinite_input_rejected(orc):
+    pr = W.di_box_problem(11)
+    l = pr.l.copy()
+    l[3, 4] = np.nan
+    with pytest.raises(FloatingPointError):
+        orc.solve(pr.grid, pr.dyn, l, **orc.problem_opts(pr))
