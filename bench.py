@@ -1,0 +1,172 @@
+"""Benchmark: warm-started HJI reachability solves on one MI355X.
+
+One benchmark step is one complete warm-started solve of the 3-D Dubins car on a 101^3 grid
+([-5,5]^2 x [-pi,pi), heading periodic): WENO5 + TVD-RK3 at CFL 0.5 in FP32 until the max-norm
+change is below the FP32 threshold, then the FP64 polish to 1e-6.  The warm start k is the
+solution with the disturbance bound halved (0.05 -> 0.1; exact by Theorem 2).  Inputs (l, k) are
+resident in device memory before the timed region starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  `value` is grid-point updates per second over the timed solves (every
+node advanced one full time step, FP32 and FP64 steps alike).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FP32 operations per node per stage of the WENO5 + Lax-Friedrichs operator on the
+# Dubins car, counted from the scheme's definition (each add, multiply, abs, max, reciprocal = 1):
+#   per dimension: 6 first differences (6 sub + 6 scale) = 12; two WENO5 derivatives at 84 each
+#   (candidates 15, second differences 9, third-order terms 9, smoothness 15, eps 11, weights 17,
+#   combination 8) = 168; average and jump of D-/D+ = 4                       -> 184 per dim
+#   Hamiltonian with dissipation coefficients = 20; dissipation sum = 6; stage combination = 5
+FLOP_PER_NODE_STAGE_DUBINS_WENO5 = 3 * 184 + 20 + 6 + 5          # = 583
+# Algorithmic HBM bytes per node per RK3 step in FP32 (no halo re-reads): stage 1 reads V, writes
+# V1 (8); stage 2 reads V1, V, writes V2 (12); stage 3 reads V2, V, l, writes V (16).
+BYTES_PER_NODE_STEP_RK3_FP32 = 36
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (packed FMA) peak
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=101, help="grid side (default 101)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(p, npts, seconds):
+    """The FP64 oracle, as it stands, timed on the host: full TVD-RK3 steps of the same grid."""
+    import numpy as np
+
+    import oracle
+
+    opts = oracle.problem_opts(p)
+    dt = oracle.cfl_dt(p.grid, p.dyn, p.cfl)
+    V = p.l.copy()
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        V, _ = oracle.step(p.grid, p.dyn, V, p.l, dt, spatial=opts["spatial"], temporal=opts["temporal"])
+        steps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    el = time.perf_counter() - t0
+    assert np.all(np.isfinite(V))
+    return {"value": steps * npts / el, "unit": "grid-point updates/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{steps} FP64 WENO5+TVD-RK3 steps of the {p.grid.n[0]}^3 Dubins grid from V=l "
+                      f"({el:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_1903_07715_amd import hjr
+    from paper_1903_07715_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    n = args.n
+    p = W.dubins_problem(n, dbar=0.1)
+    q = W.dubins_problem(n, dbar=0.05)
+    npts = p.grid.size
+    opts = hjr.problem_options(p, precision=hjr.FP32_POLISH64)
+    stream = torch.cuda.Stream()
+    l_t = torch.tensor(p.l, device=dev)
+    lq_t = torch.tensor(q.l, device=dev)
+    k_t = torch.empty_like(l_t)
+    V_t = torch.empty_like(l_t)
+    # warm-start function: the GPU solution of the smaller-disturbance problem
+    hjr.solve_device(q.grid, q.dyn, lq_t, None, k_t, stream=stream, **opts)
+    torch.cuda.synchronize()
+
+    def run(warm: bool):
+        return hjr.solve_device(p.grid, p.dyn, l_t, k_t if warm else None, V_t, stream=stream, **opts)
+
+    for _ in range(args.warmup):
+        run(True)
+    torch.cuda.synchronize()
+
+    hjr.profile_read(reset=True)
+    hjr.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    updates = 0
+    res = None
+    for _ in range(args.steps):
+        res, st = run(True)
+        updates += (res["iterations"] + res["polish_iterations"]) * npts
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    hjr.profile_enable(False)
+    prof = hjr.profile_read(reset=True)
+
+    # cold solves on the same problem, for the warm/cold comparison (not part of `value`)
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    cres = None
+    for _ in range(args.steps):
+        cres, _ = run(False)
+    torch.cuda.synchronize()
+    cel = time.perf_counter() - c0
+
+    s32 = prof["stage32"]
+    launches = sum(s["launches"] for s in s32)
+    kms = sum(s["ms"] for s in s32)
+    avg_s = kms / launches / 1e3 if launches else float("nan")
+    flops = FLOP_PER_NODE_STAGE_DUBINS_WENO5 * npts
+    achieved_tflops = flops / avg_s / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "kernel": "stage_kernel<float> (WENO5 + LF + TVD-RK3 stage, Dubins 3-D)",
+                "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+                "algorithmic_gbs": round(BYTES_PER_NODE_STEP_RK3_FP32 / 3 * npts / avg_s / 1e9, 1)}
+    line = {
+        "metric": "grid-point updates/s (warm-started solve)",
+        "value": updates / el,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"dubins3d-{n}^3-weno5-tvdrk3-fp32-polish64-warm", "grid": [n, n, n],
+                   "points": npts, "cfl": p.cfl, "tol": p.tol},
+        "warm_solves_per_s": args.steps / el,
+        "cold_solves_per_s": args.steps / cel,
+        "warm_iterations": [res["iterations"], res["polish_iterations"]],
+        "cold_iterations": [cres["iterations"], cres["polish_iterations"]],
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(p, npts, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,243 @@
+/*
+ * hjr.h -- C ABI of libhjr, the gfx950 (AMD Instinct MI355X) solver for the grid update of the
+ * HJI variational inequality used by warm-start reachability.
+ *
+ * Method: Herbert, Ghosh, Bansal, Tomlin, "Reachability-Based Safety Guarantees using Efficient
+ * Initializations".  Given dynamics x' = f(x, u, d) with compact control and disturbance sets
+ * (Sec. II-A, eq. (1)) and a target function l whose zero sublevel set is the unsafe set
+ * (Sec. II-B.1), the library marches the variational inequality min{D_t V + H, l - V} = 0
+ * (eq. (7)), H = max_u min_d <grad V, f> (eq. (6)), backwards in time on a grid until V stops
+ * changing.  It starts from V = l (standard reachability, eq. (12)) or from a caller-supplied
+ * warm-start function k (eqs. (13)-(14)); a warm start is applied as min(k, l), the effective
+ * initial value used in the proof of Theorem 1 (case b).  The result is the converged value
+ * function V*; the unsafe set (backward reachable tube) is {V* <= 0} (Sec. II-B.1).
+ *
+ * Discrete scheme (the paper leaves it to a level-set toolbox):
+ *   derivatives   HJR_UPWIND1: one-sided first differences; HJR_WENO5: fifth-order WENO of Jiang
+ *                 and Peng.  Non-periodic dims extend the grid by linear extrapolation (so a
+ *                 first difference beyond an edge equals the nearest interior one); periodic
+ *                 dims wrap.
+ *   Hamiltonian   Lax-Friedrichs: L(V) = H(x, (D-V + D+V)/2) + sum_i alpha_i(x) (D+_i V - D-_i V)/2
+ *                 with alpha_i(x) = max over (u, d) of |f_i(x, u, d)|.
+ *   time          backward time s = -t; HJR_EULER: V + dt L(V); HJR_TVDRK3: the three-stage
+ *                 Shu-Osher scheme.  dt = cfl / max_x sum_i alpha_i(x)/dx_i (fixed per solve).
+ *   projection    V <- min(l, V) after every full step (eq. (7)).
+ *   stopping      HJR_CONV_PER_STEP: stop when max_x |V^{n+1} - V^n| < tol.
+ *                 HJR_CONV_PER_INTERVAL: steps are cut to end on multiples of dt_report and the
+ *                 change across a whole interval is tested (the rule of Sec. IV: interval 0.01,
+ *                 threshold 0.001).  Also stop at max_iter steps or at t_max (t_max > 0).
+ *   precision     HJR_FP64: everything in FP64.  HJR_FP32: stencil, Hamiltonian and RK in FP32
+ *                 (time, dt and the convergence test in FP64).  HJR_FP32_POLISH64: FP32 until
+ *                 the change is below tol_fp32, then FP64 from min(l, V32 + polish_shift) until
+ *                 it is below tol; starting above the FP64 solution makes the polish exact by
+ *                 Theorem 2.
+ *
+ * Memory layout: every grid array is dense, C order (the last dimension is contiguous), one
+ * double per node.  Node j of dim i is at lo[i] + j*dx[i]; dx = (hi-lo)/(n-1) for a non-periodic
+ * dim (both ends are nodes) and (hi-lo)/n for a periodic dim (hi excluded).
+ *
+ * Errors: every entry point returns an hjr_status.  Negative values are errors (nothing was
+ * written to the outputs), positive values are warnings with valid outputs.  hjr_last_error()
+ * returns a thread-local description of the last error on the calling thread.  Arguments are
+ * validated before any device work; a non-finite l or k is reported as HJR_ERR_NONFINITE.
+ *
+ * Ownership: the library never keeps a caller pointer beyond the call, except on the submit
+ * path, where l_dev, k_dev and V_dev must stay valid until hjr_poll reports the ticket done.
+ * Host pointers may be pageable memory.
+ *
+ * Threads: hjr_solve, hjr_solve_device, hjr_batch_solve and the kernel-level entry points may be
+ * called from several threads.  One hjr_ctx must be used from one thread at a time.
+ */
+#ifndef HJR_H
+#define HJR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HJR_ABI_VERSION 1
+#define HJR_MAX_DIM 6
+#define HJR_MAX_PARAMS 16
+
+typedef int32_t hjr_status;
+enum {
+    HJR_OK = 0,
+    HJR_NOT_CONVERGED = 1,   /* max_iter reached; V is the last iterate */
+    HJR_PENDING = 2,         /* hjr_poll: the ticket is still running */
+    HJR_HORIZON = 3,         /* t_max reached (finite-horizon solve); V is V(., -t_max) */
+    HJR_ERR_INVALID_ARG = -1,
+    HJR_ERR_UNSUPPORTED = -2,
+    HJR_ERR_NONFINITE = -3,
+    HJR_ERR_OOM = -4,
+    HJR_ERR_DEVICE = -5,
+    HJR_ERR_BUDGET = -6,     /* a request can never fit the context's memory budget */
+    HJR_ERR_UNKNOWN_TICKET = -7
+};
+
+/* Grid.  ndim in 1..6 and equal to the model's state dimension; n[i] >= 3 (>= 7 with WENO5);
+ * lo[i] < hi[i]; the product of n must stay below 2^31. */
+typedef struct {
+    int32_t ndim;
+    int32_t n[HJR_MAX_DIM];
+    double lo[HJR_MAX_DIM];
+    double hi[HJR_MAX_DIM];
+    uint32_t periodic_mask;  /* bit i set: dim i is periodic */
+} hjr_grid;
+
+/* Models (state order in brackets) and parameter layouts:
+ *  HJR_DYN_DOUBLE_INTEGRATOR [x1, x2]: x1' = x2 + d, x2' = b u; |u| <= ubar, |d| <= dbar
+ *      (the running example of Sec. II-A, eq. (2)).       params = {ubar, b, dbar}
+ *  HJR_DYN_DUBINS3 [x, y, theta]: x' = v cos(theta) + d1, y' = v sin(theta) + d2, theta' = u;
+ *      |u| <= ubar, |d_i| <= dbar_i.                        params = {v, ubar, dbar1, dbar2}
+ *  HJR_DYN_UNICYCLE4 [x, y, theta, v]: x' = v cos(theta) + d1, y' = v sin(theta) + d2,
+ *      theta' = u1, v' = u2; |u1| <= ubar1, |u2| <= ubar2; (d1, d2) in the disk of radius dbar
+ *      (shape 0) or the box |d_i| <= dbar (shape 1).       params = {ubar1, ubar2, dbar, shape}
+ *  HJR_DYN_QUAD6 [px, py, pz, vx, vy, vz]: p' = v, vx' = g tan(theta) + dx,
+ *      vy' = -g tan(phi) + dy, vz' = T/m - g + dz; |theta| <= theta_max, |phi| <= phi_max,
+ *      T in [Tmin, Tmax], |d_i| <= dbar_i.
+ *      params = {g, m, phi_max, theta_max, Tmin, Tmax, dbar_x, dbar_y, dbar_z} */
+enum { HJR_DYN_DOUBLE_INTEGRATOR = 1, HJR_DYN_DUBINS3 = 2, HJR_DYN_UNICYCLE4 = 3, HJR_DYN_QUAD6 = 4 };
+
+typedef struct {
+    int32_t id;
+    int32_t n_params;
+    double params[HJR_MAX_PARAMS];
+} hjr_dynamics;
+
+enum { HJR_AVOID = 0, HJR_REACH = 1 };      /* AVOID: control maximises, disturbance minimises */
+enum { HJR_UPWIND1 = 1, HJR_WENO5 = 5 };
+enum { HJR_EULER = 1, HJR_TVDRK3 = 3 };
+enum { HJR_FP64 = 0, HJR_FP32 = 1, HJR_FP32_POLISH64 = 2 };
+enum { HJR_CONV_PER_STEP = 0, HJR_CONV_PER_INTERVAL = 1 };
+
+typedef struct {
+    int32_t game;           /* HJR_AVOID (default) | HJR_REACH */
+    int32_t spatial;        /* HJR_UPWIND1 | HJR_WENO5 (default) */
+    int32_t temporal;       /* HJR_EULER | HJR_TVDRK3 (default) */
+    int32_t precision;      /* HJR_FP64 | HJR_FP32 | HJR_FP32_POLISH64 (default) */
+    int32_t conv_mode;      /* HJR_CONV_PER_STEP (default) | HJR_CONV_PER_INTERVAL */
+    int32_t steps_per_sync; /* time steps launched between host checks; 0 = adaptive */
+    double cfl;             /* in (0, 1]; default 0.5 */
+    double tol;             /* > 0; default 1e-6 */
+    double tol_fp32;        /* FP32-phase threshold; 0 = max(tol, 8 ulp_fp32(max |l|)) */
+    double polish_shift;    /* < 0 = auto (2 * tol_fp32); the FP64 polish starts at min(l, V32 + shift) */
+    double dt_report;       /* interval length of HJR_CONV_PER_INTERVAL; default 0.01 */
+    double t_max;           /* > 0: stop at this backward time (finite horizon); default 0 */
+    double dt_max;          /* > 0: cap on dt; default 0 (a vanishing flow field uses dt = 1) */
+    int64_t max_iter;       /* cap on time steps per phase; default 1000000 */
+} hjr_options;
+
+typedef struct {
+    int64_t iterations;         /* time steps of the first phase (FP32, or FP64 for HJR_FP64) */
+    int64_t polish_iterations;  /* FP64 polish time steps */
+    int64_t intervals;          /* completed report intervals (interval mode) */
+    double t_final;             /* backward time marched */
+    double last_delta;          /* last change tested against the threshold */
+    double dt;                  /* nominal CFL time step */
+    double max_abs_l;           /* max |l| over the grid */
+    double seconds;             /* wall-clock time of the device work */
+    int32_t converged;          /* 1 converged, 0 max_iter reached, 2 horizon reached */
+    int32_t pad;
+} hjr_result;
+
+/* Library information and defaults. */
+int32_t hjr_abi_version(void);
+hjr_status hjr_default_options(hjr_options *opts);
+const char *hjr_status_string(hjr_status status);
+const char *hjr_last_error(void);
+/* Number of visible devices (0 when no GPU is usable). */
+int32_t hjr_device_count(void);
+
+/* Synchronous solve with host arrays.  l: prod(n) doubles; k: prod(n) doubles or NULL (cold
+ * start); V_out: prod(n) doubles written on success or HJR_NOT_CONVERGED / HJR_HORIZON. */
+hjr_status hjr_solve(const hjr_grid *grid, const hjr_dynamics *dyn, const double *l,
+                     const double *k, const hjr_options *opts, double *V_out, hjr_result *result);
+
+/* Same, with device arrays (l_dev, k_dev nullable, V_dev) on the current device.  Work is
+ * issued on `stream` (a hipStream_t, NULL = a stream the library owns); returns when done. */
+hjr_status hjr_solve_device(const hjr_grid *grid, const hjr_dynamics *dyn, const double *l_dev,
+                            const double *k_dev, const hjr_options *opts, double *V_dev,
+                            void *stream, hjr_result *result);
+
+/* Batched solve: `count` independent problems (host arrays) advanced together, every stage of
+ * every instance in one launch per stage.  Each problem's status and result are filled in; the
+ * return value is HJR_OK if every problem converged, else the first non-OK status. */
+typedef struct {
+    hjr_grid grid;
+    hjr_dynamics dyn;
+    hjr_options opts;
+    const double *l;
+    const double *k;       /* NULL: cold */
+    double *V_out;
+    hjr_result result;     /* out */
+    hjr_status status;     /* out */
+    int32_t pad;
+} hjr_problem;
+hjr_status hjr_batch_solve(int32_t count, hjr_problem *problems);
+
+/* Kernel-level entry points (device arrays, element type FP32 when precision == HJR_FP32, else
+ * FP64).  They run exactly the kernels the solvers run.
+ *   hjr_cfl_dt: dt = cfl / max_x sum_i alpha_i(x)/dx_i (1 when that maximum is 0), capped by
+ *     dt_max > 0; computed by a device reduction.
+ *   hjr_stage_device: one time-integrator stage at every node.  Vs is the field the stencil is
+ *     applied to, Vn the field at the start of the step, l the target function, out the result:
+ *       Euler (stage 1 only): out = min(l, Vs + dt L(Vs))
+ *       TVD-RK3 stage 1: out = Vn + dt L(Vn) (Vs must equal Vn)
+ *               stage 2: out = 3/4 Vn + 1/4 (Vs + dt L(Vs))
+ *               stage 3: out = min(l, 1/3 Vn + 2/3 (Vs + dt L(Vs)))
+ *     If delta_out is not NULL and the stage ends the step, *delta_out = max |out - Vn|.
+ *     out must not alias Vs. */
+hjr_status hjr_cfl_dt(const hjr_grid *grid, const hjr_dynamics *dyn, double cfl, double dt_max,
+                      double *dt_out);
+hjr_status hjr_stage_device(const hjr_grid *grid, const hjr_dynamics *dyn, int32_t game,
+                            int32_t spatial, int32_t temporal, int32_t stage, int32_t precision,
+                            double dt, const void *Vs, const void *Vn, const void *l, void *out,
+                            double *delta_out, void *stream);
+
+/* Kernel timing: while enabled (process-wide), the solvers bracket every stage-kernel launch
+ * with HIP events on the stream it runs on and accumulate the elapsed times; hjr_profile_read
+ * returns the totals since the last reset.  `nodes` counts grid nodes covered by the launches'
+ * tile lists (including nodes of instances that had already finished). */
+typedef struct {
+    int64_t launches;
+    int64_t nodes;
+    double ms;
+} hjr_kernel_time;
+typedef struct {
+    hjr_kernel_time stage32[3];   /* FP32 stage kernels, by RK stage (Euler uses [0]) */
+    hjr_kernel_time stage64[3];   /* FP64 stage kernels */
+} hjr_profile;
+hjr_status hjr_profile_enable(int32_t on);
+hjr_status hjr_profile_read(hjr_profile *out, int32_t reset);
+
+/* Serving context: requests with device arrays are admitted while their working memory fits
+ * `hbm_budget_bytes` (0 = 90% of free device memory) and advance together, in the same batched
+ * launches, with requests already running; a request that arrives while others run joins at the
+ * next step boundary.  A worker thread owned by the context drives the device. */
+typedef struct hjr_ctx hjr_ctx;
+hjr_status hjr_ctx_create(int32_t device, size_t hbm_budget_bytes, hjr_ctx **out);
+hjr_status hjr_submit(hjr_ctx *ctx, const hjr_grid *grid, const hjr_dynamics *dyn,
+                      const double *l_dev, const double *k_dev, const hjr_options *opts,
+                      double *V_dev, int64_t *ticket);
+/* HJR_PENDING while running; otherwise the request's final status (and result).  A finished
+ * ticket is forgotten after it has been polled once. */
+hjr_status hjr_poll(hjr_ctx *ctx, int64_t ticket, hjr_result *result);
+/* Block until every submitted request has finished. */
+hjr_status hjr_ctx_drain(hjr_ctx *ctx);
+/* Counters: requests admitted/finished, peak bytes in use, batched steps launched. */
+typedef struct {
+    int64_t admitted, finished, queued, running;
+    int64_t bytes_in_use, bytes_peak, budget;
+    int64_t chunks, launches;
+} hjr_ctx_stats;
+hjr_status hjr_ctx_get_stats(hjr_ctx *ctx, hjr_ctx_stats *stats);
+hjr_status hjr_ctx_destroy(hjr_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HJR_H */

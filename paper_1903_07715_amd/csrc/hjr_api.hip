@@ -1,0 +1,1325 @@
+// hjr_api.hip -- host side of libhjr: validation, device memory, the batched step engine, the
+// C ABI declared in include/hjr.h and the serving context.
+//
+// One Engine advances a set of solve instances together.  Each instance owns its device
+// buffers and a SolveState slot; the engine keeps the Inst descriptors and the tile lists of the
+// FP32-phase and FP64-phase instances in device memory.  A chunk is m time steps issued without
+// host round trips: per step, one launch per RK stage and precision over all tiles, then one
+// bookkeeping launch that advances every instance's clock, tests its convergence and freezes it
+// when done (frozen instances make every later kernel return at once).  After a chunk the host
+// reads all states back with one copy, hands converged FP32 instances over to the FP64 polish,
+// finishes completed instances, admits waiting ones and rebuilds the tile lists.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/hjr.h"
+#include "fastdiv.hpp"
+#include "hjr_kernels.hpp"
+
+namespace hjr {
+
+// --------------------------------------------------------------------------------------------
+// Errors
+// --------------------------------------------------------------------------------------------
+
+static thread_local std::string g_last_error;
+
+static hjr_status fail(hjr_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define HJR_HIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(HJR_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));        \
+    } while (0)
+
+static double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// --------------------------------------------------------------------------------------------
+// Kernel timing (process-wide)
+// --------------------------------------------------------------------------------------------
+
+static std::atomic<int> g_profile_on{0};
+static std::mutex g_profile_mu;
+static hjr_profile g_profile{};
+
+// --------------------------------------------------------------------------------------------
+// Validation
+// --------------------------------------------------------------------------------------------
+
+static int dyn_ndim(int id)
+{
+    switch (id) {
+    case HJR_DYN_DOUBLE_INTEGRATOR: return 2;
+    case HJR_DYN_DUBINS3: return 3;
+    case HJR_DYN_UNICYCLE4: return 4;
+    case HJR_DYN_QUAD6: return 6;
+    default: return -1;
+    }
+}
+
+static int dyn_nparams(int id)
+{
+    switch (id) {
+    case HJR_DYN_DOUBLE_INTEGRATOR: return 3;
+    case HJR_DYN_DUBINS3: return 4;
+    case HJR_DYN_UNICYCLE4: return 4;
+    case HJR_DYN_QUAD6: return 9;
+    default: return -1;
+    }
+}
+
+static hjr_status validate(const hjr_grid *g, const hjr_dynamics *dy, int spatial, uint64_t *npts_out)
+{
+    if (!g || !dy) return fail(HJR_ERR_INVALID_ARG, "grid and dynamics must not be NULL");
+    if (g->ndim < 1 || g->ndim > HJR_MAX_DIM) return fail(HJR_ERR_INVALID_ARG, "ndim %d out of range", g->ndim);
+    const int nd = dyn_ndim(dy->id);
+    if (nd < 0) return fail(HJR_ERR_UNSUPPORTED, "unknown dynamics id %d", dy->id);
+    if (nd != g->ndim)
+        return fail(HJR_ERR_INVALID_ARG, "dynamics %d has %d states but the grid has %d dims", dy->id, nd, g->ndim);
+    if (dy->n_params != dyn_nparams(dy->id))
+        return fail(HJR_ERR_INVALID_ARG, "dynamics %d takes %d parameters, got %d", dy->id, dyn_nparams(dy->id),
+                    dy->n_params);
+    for (int i = 0; i < dy->n_params; ++i)
+        if (!std::isfinite(dy->params[i])) return fail(HJR_ERR_INVALID_ARG, "parameter %d is not finite", i);
+    const double *q = dy->params;
+    switch (dy->id) {
+    case HJR_DYN_DOUBLE_INTEGRATOR:
+        if (q[0] < 0 || q[2] < 0) return fail(HJR_ERR_INVALID_ARG, "bounds must be non-negative");
+        break;
+    case HJR_DYN_DUBINS3:
+        if (q[1] < 0 || q[2] < 0 || q[3] < 0) return fail(HJR_ERR_INVALID_ARG, "bounds must be non-negative");
+        break;
+    case HJR_DYN_UNICYCLE4:
+        if (q[0] < 0 || q[1] < 0 || q[2] < 0 || (q[3] != 0.0 && q[3] != 1.0))
+            return fail(HJR_ERR_INVALID_ARG, "bad unicycle parameters");
+        break;
+    case HJR_DYN_QUAD6:
+        if (!(q[1] > 0) || q[2] < 0 || q[3] < 0 || q[2] >= 1.5 || q[3] >= 1.5 || q[4] > q[5] || q[6] < 0 ||
+            q[7] < 0 || q[8] < 0)
+            return fail(HJR_ERR_INVALID_ARG, "bad quadrotor parameters");
+        break;
+    }
+    uint64_t N = 1;
+    for (int d = 0; d < g->ndim; ++d) {
+        const int minn = spatial == HJR_WENO5 ? 7 : 3;
+        if (g->n[d] < minn) return fail(HJR_ERR_INVALID_ARG, "dim %d has %d nodes (< %d)", d, g->n[d], minn);
+        if (!std::isfinite(g->lo[d]) || !std::isfinite(g->hi[d]) || !(g->hi[d] > g->lo[d]))
+            return fail(HJR_ERR_INVALID_ARG, "dim %d: need lo < hi", d);
+        N *= (uint64_t)g->n[d];
+        if (N >= (1ull << 31)) return fail(HJR_ERR_UNSUPPORTED, "grid has 2^31 or more nodes");
+    }
+    if (g->periodic_mask >> g->ndim) return fail(HJR_ERR_INVALID_ARG, "periodic_mask names a missing dim");
+    *npts_out = N;
+    return HJR_OK;
+}
+
+static hjr_status validate_opts(const hjr_options *o)
+{
+    if (!o) return fail(HJR_ERR_INVALID_ARG, "options must not be NULL");
+    if (o->game != HJR_AVOID && o->game != HJR_REACH) return fail(HJR_ERR_INVALID_ARG, "bad game %d", o->game);
+    if (o->spatial != HJR_UPWIND1 && o->spatial != HJR_WENO5)
+        return fail(HJR_ERR_INVALID_ARG, "bad spatial scheme %d", o->spatial);
+    if (o->temporal != HJR_EULER && o->temporal != HJR_TVDRK3)
+        return fail(HJR_ERR_INVALID_ARG, "bad temporal scheme %d", o->temporal);
+    if (o->precision < HJR_FP64 || o->precision > HJR_FP32_POLISH64)
+        return fail(HJR_ERR_INVALID_ARG, "bad precision %d", o->precision);
+    if (o->conv_mode != HJR_CONV_PER_STEP && o->conv_mode != HJR_CONV_PER_INTERVAL)
+        return fail(HJR_ERR_INVALID_ARG, "bad conv_mode %d", o->conv_mode);
+    if (!(o->cfl > 0.0) || !(o->cfl <= 1.0)) return fail(HJR_ERR_INVALID_ARG, "cfl must be in (0, 1]");
+    if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return fail(HJR_ERR_INVALID_ARG, "tol must be > 0");
+    if (!(o->tol_fp32 >= 0.0)) return fail(HJR_ERR_INVALID_ARG, "tol_fp32 must be >= 0");
+    if (o->conv_mode == HJR_CONV_PER_INTERVAL && !(o->dt_report > 0.0))
+        return fail(HJR_ERR_INVALID_ARG, "interval mode needs dt_report > 0");
+    if (!(o->t_max >= 0.0) || !(o->dt_max >= 0.0)) return fail(HJR_ERR_INVALID_ARG, "t_max, dt_max must be >= 0");
+    if (o->max_iter < 0) return fail(HJR_ERR_INVALID_ARG, "max_iter must be >= 0");
+    if (o->steps_per_sync < 0) return fail(HJR_ERR_INVALID_ARG, "steps_per_sync must be >= 0");
+    return HJR_OK;
+}
+
+// --------------------------------------------------------------------------------------------
+// Device memory: a process-wide caching pool (allocation is slow next to a solve of a small grid)
+// --------------------------------------------------------------------------------------------
+
+class Pool {
+public:
+    static Pool &get()
+    {
+        static Pool *p = new Pool();  // never destroyed: cached blocks live until process exit
+        return *p;
+    }
+    hipError_t alloc(void **ptr, size_t bytes)
+    {
+        bytes = round(bytes);
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            auto &fl = free_[key(dev, bytes)];
+            if (!fl.empty()) {
+                *ptr = fl.back();
+                fl.pop_back();
+                size_[*ptr] = bytes;
+                return hipSuccess;
+            }
+        }
+        hipError_t e = hipMalloc(ptr, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            trim(dev);
+            e = hipMalloc(ptr, bytes);
+        }
+        if (e == hipSuccess) {
+            std::lock_guard<std::mutex> g(mu_);
+            size_[*ptr] = bytes;
+            dev_[*ptr] = dev;
+        }
+        return e;
+    }
+    void release(void *ptr)
+    {
+        if (!ptr) return;
+        std::lock_guard<std::mutex> g(mu_);
+        auto it = size_.find(ptr);
+        if (it == size_.end()) return;
+        free_[key(dev_[ptr], it->second)].push_back(ptr);
+        size_.erase(it);
+    }
+
+private:
+    static size_t round(size_t b)
+    {
+        size_t r = 1 << 20;
+        while (r < b) r <<= 1;
+        return r;
+    }
+    static uint64_t key(int dev, size_t b) { return ((uint64_t)dev << 56) | (uint64_t)b; }
+    void trim(int dev)
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        for (auto &kv : free_) {
+            if ((int)(kv.first >> 56) != dev) continue;
+            for (void *p : kv.second) {
+                (void)hipFree(p);
+                dev_.erase(p);
+            }
+            kv.second.clear();
+        }
+    }
+    std::mutex mu_;
+    std::map<uint64_t, std::vector<void *>> free_;
+    std::unordered_map<void *, size_t> size_;
+    std::unordered_map<void *, int> dev_;
+};
+
+// --------------------------------------------------------------------------------------------
+// One solve instance
+// --------------------------------------------------------------------------------------------
+
+struct Request {
+    hjr_grid grid;
+    hjr_dynamics dyn;
+    hjr_options opts;
+    const double *l_dev = nullptr;   // FP64 target function (caller or owned)
+    const double *k_dev = nullptr;
+    double *V_dev = nullptr;         // FP64 output (caller or owned)
+    uint64_t npts = 0;
+    size_t bytes = 0;                // working memory
+    void *mem = nullptr;             // owned working buffer
+    Inst inst{};
+    int slot = -1;
+    int phase = 0;                   // 0 first phase, 1 polish
+    bool fp32_first = false;
+    int64_t iters0 = 0;
+    hjr_result result{};
+    hjr_status status = HJR_PENDING;
+    int64_t ticket = 0;
+    double t_submit = 0.0, t_start = 0.0;
+    bool done = false;
+};
+
+static void make_constants(const hjr_dynamics &dy, double c[8])
+{
+    for (int i = 0; i < 8; ++i) c[i] = 0.0;
+    const double *q = dy.params;
+    switch (dy.id) {
+    case HJR_DYN_DOUBLE_INTEGRATOR:
+        c[0] = std::fabs(q[1]) * q[0];
+        c[1] = q[2];
+        break;
+    case HJR_DYN_DUBINS3:
+    case HJR_DYN_UNICYCLE4:
+        for (int i = 0; i < 4; ++i) c[i] = q[i];
+        break;
+    case HJR_DYN_QUAD6: {
+        const double g = q[0], m = q[1];
+        c[0] = g * std::tan(q[3]);
+        c[1] = g * std::tan(q[2]);
+        c[2] = q[5] / m - g;
+        c[3] = q[4] / m - g;
+        c[4] = q[6];
+        c[5] = q[7];
+        c[6] = q[8];
+        c[7] = std::max(std::fabs(c[2]), std::fabs(c[3]));
+        break;
+    }
+    }
+}
+
+static double grid_dx(const hjr_grid &g, int d)
+{
+    return ((g.periodic_mask >> d) & 1u) ? (g.hi[d] - g.lo[d]) / g.n[d] : (g.hi[d] - g.lo[d]) / (g.n[d] - 1);
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Working memory of one request, carved from one pool block.
+struct Layout {
+    size_t V32, A32, B32, l32, Vs32, A64, B64, Vs64, V64, l64, k64, tab32, tab64, total;
+    int ntab;
+};
+
+static Layout plan_layout(const Request &r, bool own_io)
+{
+    Layout L{};
+    const size_t N = r.npts;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+    const bool fp32 = r.opts.precision != HJR_FP64;
+    const bool fp64 = r.opts.precision != HJR_FP32;
+    const bool interval = r.opts.conv_mode == HJR_CONV_PER_INTERVAL;
+    const size_t none = (size_t)-1;
+    L.V32 = fp32 ? take(N * 4) : none;
+    L.A32 = fp32 ? take(N * 4) : none;
+    L.B32 = fp32 && r.opts.temporal == HJR_TVDRK3 ? take(N * 4) : none;
+    L.l32 = fp32 ? take(N * 4) : none;
+    L.Vs32 = fp32 && interval ? take(N * 4) : none;
+    L.A64 = fp64 ? take(N * 8) : none;
+    L.B64 = fp64 && r.opts.temporal == HJR_TVDRK3 ? take(N * 8) : none;
+    L.Vs64 = fp64 && interval ? take(N * 8) : none;
+    L.V64 = own_io ? take(N * 8) : none;
+    L.l64 = own_io ? take(N * 8) : none;
+    L.k64 = own_io ? take(N * 8) : none;
+    int nt = 0;
+    for (int d = 0; d < r.grid.ndim; ++d) nt += r.grid.n[d];
+    nt += 2 * r.grid.n[std::min(2, r.grid.ndim - 1)];
+    L.ntab = nt;
+    L.tab32 = take((size_t)nt * 4);
+    L.tab64 = take((size_t)nt * 8);
+    L.total = off;
+    return L;
+}
+
+static size_t request_bytes(const Request &r, bool own_io) { return plan_layout(r, own_io).total; }
+
+// Fill the Inst descriptor and the coordinate tables (host staging `tab64`, `tab32`).
+static void build_inst(Request &r, char *base, const Layout &L, std::vector<double> &tab64,
+                       std::vector<float> &tab32, SolveState *state_dev)
+{
+    Inst &I = r.inst;
+    std::memset(&I, 0, sizeof I);
+    const hjr_grid &g = r.grid;
+    I.ndim = g.ndim;
+    I.dyn = r.dyn.id;
+    I.spatial = r.opts.spatial;
+    I.temporal = r.opts.temporal;
+    I.game = r.opts.game;
+    I.nstages = r.opts.temporal == HJR_TVDRK3 ? 3 : 1;
+    I.npts = (uint32_t)r.npts;
+    I.periodic = g.periodic_mask;
+    uint32_t s = 1;
+    for (int d = g.ndim - 1; d >= 0; --d) {
+        I.n[d] = g.n[d];
+        I.stride[d] = s;
+        s *= (uint32_t)g.n[d];
+        FastDivParams p = fastdiv_params((uint32_t)g.n[d]);
+        I.div[d].mul = p.mul;
+        I.div[d].shift = p.shift;
+        I.div[d].d = (uint32_t)g.n[d];
+        const double dx = grid_dx(g, d);
+        I.inv_dx64[d] = 1.0 / dx;
+        I.inv_dx32[d] = (float)(1.0 / dx);
+    }
+    double c[8];
+    make_constants(r.dyn, c);
+    for (int i = 0; i < 8; ++i) {
+        I.c64[i] = c[i];
+        I.c32[i] = (float)c[i];
+    }
+    tab64.assign((size_t)L.ntab, 0.0);
+    int off = 0;
+    for (int d = 0; d < g.ndim; ++d) {
+        I.coord_off[d] = off;
+        const double dx = grid_dx(g, d);
+        for (int j = 0; j < g.n[d]; ++j) tab64[off + j] = g.lo[d] + (double)j * dx;
+        off += g.n[d];
+    }
+    I.trig_off = -1;
+    if (r.dyn.id == HJR_DYN_DUBINS3 || r.dyn.id == HJR_DYN_UNICYCLE4) {
+        I.trig_off = off;
+        const int nt = g.n[2];
+        for (int j = 0; j < nt; ++j) {
+            const double th = tab64[I.coord_off[2] + j];
+            tab64[off + j] = std::cos(th);
+            tab64[off + nt + j] = std::sin(th);
+        }
+    }
+    tab32.resize(tab64.size());
+    for (size_t i = 0; i < tab64.size(); ++i) tab32[i] = (float)tab64[i];
+    auto at = [&](size_t o) -> char * { return o == (size_t)-1 ? nullptr : base + o; };
+    I.tab32 = (const float *)at(L.tab32);
+    I.tab64 = (const double *)at(L.tab64);
+    I.V32 = (float *)at(L.V32);
+    I.A32 = (float *)at(L.A32);
+    I.B32 = (float *)at(L.B32);
+    I.l32 = (const float *)at(L.l32);
+    I.Vs32 = (float *)at(L.Vs32);
+    I.A64 = (double *)at(L.A64);
+    I.B64 = (double *)at(L.B64);
+    I.Vs64 = (double *)at(L.Vs64);
+    I.V64 = r.V_dev;
+    I.l64 = r.l_dev;
+    I.state = state_dev;
+}
+
+static SolveState initial_state(const Request &r)
+{
+    SolveState st;
+    std::memset(&st, 0, sizeof st);
+    st.tol_final = r.opts.tol;
+    st.tol = r.opts.tol;
+    st.tol32_req = r.opts.tol_fp32;
+    st.t_max = r.opts.t_max;
+    st.dt_report = r.opts.dt_report;
+    st.dt_max = r.opts.dt_max;
+    st.cfl = r.opts.cfl;
+    st.max_iter = r.opts.max_iter;
+    st.conv_mode = r.opts.conv_mode;
+    st.last_delta = INFINITY;
+    st.done = kRunning;  // set properly by setup_kernel
+    return st;
+}
+
+// --------------------------------------------------------------------------------------------
+// Engine
+// --------------------------------------------------------------------------------------------
+
+class Engine {
+public:
+    explicit Engine(int capacity) : cap_(capacity) {}
+    ~Engine() { release(); }
+
+    hjr_status init(hipStream_t stream)
+    {
+        HJR_HIP(hipGetDevice(&device_));
+        if (stream) {
+            stream_ = stream;
+        } else {
+            HJR_HIP(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
+            own_stream_ = true;
+        }
+        HJR_HIP(Pool::get().alloc((void **)&d_states_, sizeof(SolveState) * cap_));
+        HJR_HIP(Pool::get().alloc((void **)&d_insts_, sizeof(Inst) * cap_));
+        HJR_HIP(hipHostMalloc((void **)&h_states_, sizeof(SolveState) * cap_, hipHostMallocDefault));
+        HJR_HIP(hipHostMalloc((void **)&h_insts_, sizeof(Inst) * cap_, hipHostMallocDefault));
+        std::memset(h_insts_, 0, sizeof(Inst) * cap_);
+        // idle slots: a frozen state so step_end skips them
+        for (int i = 0; i < cap_; ++i) {
+            std::memset(&h_states_[i], 0, sizeof(SolveState));
+            h_states_[i].done = 99;
+            h_insts_[i].state = d_states_ + i;
+        }
+        HJR_HIP(hipMemcpyAsync(d_states_, h_states_, sizeof(SolveState) * cap_, hipMemcpyHostToDevice, stream_));
+        HJR_HIP(hipMemcpyAsync(d_insts_, h_insts_, sizeof(Inst) * cap_, hipMemcpyHostToDevice, stream_));
+        HJR_HIP(hipStreamSynchronize(stream_));
+        slots_.assign(cap_, nullptr);
+        hist_.assign(cap_, Hist{});
+        HJR_HIP(hipDeviceGetAttribute(&cus_, hipDeviceAttributeMultiprocessorCount, device_));
+        return HJR_OK;
+    }
+
+    void release()
+    {
+        if (stream_) (void)hipStreamSynchronize(stream_);
+        for (EvRec &e : evs_) {
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
+        }
+        evs_.clear();
+        for (Request *r : slots_)
+            if (r) drop(r);
+        Pool::get().release(d_states_);
+        Pool::get().release(d_insts_);
+        Pool::get().release(d_tiles32_);
+        Pool::get().release(d_tiles64_);
+        d_states_ = nullptr;
+        d_insts_ = nullptr;
+        d_tiles32_ = d_tiles64_ = nullptr;
+        if (h_states_) (void)hipHostFree(h_states_);
+        if (h_insts_) (void)hipHostFree(h_insts_);
+        if (h_tiles_) (void)hipHostFree(h_tiles_);
+        h_states_ = nullptr;
+        h_insts_ = nullptr;
+        h_tiles_ = nullptr;
+        if (own_stream_ && stream_) (void)hipStreamDestroy(stream_);
+        stream_ = nullptr;
+    }
+
+    hipStream_t stream() const { return stream_; }
+    int active() const { return nactive_; }
+    bool has_free_slot() const { return nactive_ < cap_; }
+    int64_t launches() const { return launches_; }
+    int64_t chunks() const { return chunks_; }
+    void set_max_blocks(int b) { max_blocks_ = b; }
+
+    // Start a request: allocate, upload descriptors and tables, launch init + setup.
+    // own_io: the library owns l/k/V device copies (host-pointer path); host arrays given.
+    hjr_status admit(Request *r, bool own_io, const double *l_host, const double *k_host)
+    {
+        int slot = -1;
+        for (int i = 0; i < cap_; ++i)
+            if (!slots_[i]) {
+                slot = i;
+                break;
+            }
+        if (slot < 0) return fail(HJR_ERR_INVALID_ARG, "engine is full");
+        Layout L = plan_layout(*r, own_io);
+        r->bytes = L.total;
+        HJR_HIP(Pool::get().alloc(&r->mem, L.total));
+        char *base = (char *)r->mem;
+        if (own_io) {
+            r->V_dev = (double *)(base + L.V64);
+            r->l_dev = (const double *)(base + L.l64);
+            r->k_dev = k_host ? (const double *)(base + L.k64) : nullptr;
+            HJR_HIP(hipMemcpyAsync((void *)r->l_dev, l_host, r->npts * 8, hipMemcpyHostToDevice, stream_));
+            if (k_host)
+                HJR_HIP(hipMemcpyAsync((void *)r->k_dev, k_host, r->npts * 8, hipMemcpyHostToDevice, stream_));
+        }
+        std::vector<double> t64;
+        std::vector<float> t32;
+        build_inst(*r, base, L, t64, t32, d_states_ + slot);
+        HJR_HIP(hipMemcpyAsync((void *)r->inst.tab64, t64.data(), t64.size() * 8, hipMemcpyHostToDevice, stream_));
+        HJR_HIP(hipMemcpyAsync((void *)r->inst.tab32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice, stream_));
+        // the host vectors must outlive the copies
+        HJR_HIP(hipStreamSynchronize(stream_));
+        r->slot = slot;
+        r->phase = 0;
+        hist_[slot] = Hist{};
+        r->fp32_first = r->opts.precision != HJR_FP64;
+        slots_[slot] = r;
+        ++nactive_;
+        h_insts_[slot] = r->inst;
+        h_states_[slot] = initial_state(*r);
+        HJR_HIP(hipMemcpyAsync(d_insts_ + slot, &h_insts_[slot], sizeof(Inst), hipMemcpyHostToDevice, stream_));
+        HJR_HIP(hipMemcpyAsync(d_states_ + slot, &h_states_[slot], sizeof(SolveState), hipMemcpyHostToDevice,
+                               stream_));
+        HJR_HIP(launch_init(d_insts_, slot, (uint32_t)r->npts, r->l_dev, r->k_dev, r->fp32_first, stream_));
+        r->t_start = now_s();
+        dirty_ = true;
+        return HJR_OK;
+    }
+
+    // Issue m steps for every running instance, then read the states back.
+    hjr_status run_chunk(int m)
+    {
+        if (dirty_) {
+            hjr_status s = rebuild();
+            if (s != HJR_OK) return s;
+        }
+        const int ninst = top_slot_ + 1;
+        const bool prof = g_profile_on.load() != 0;
+        nev_ = 0;
+        for (int step = 0; step < m; ++step) {
+            for (int stage = 0; stage < max_stages_; ++stage) {
+                for (int prec = 0; prec < 2; ++prec) {
+                    const int nt = prec ? n64_ : n32_;
+                    if (nt <= 0) continue;
+                    hipEvent_t a = nullptr, b = nullptr;
+                    if (prof) {
+                        hjr_status s = event_pair(&a, &b, prec, stage, (int64_t)nt * kBlock);
+                        if (s != HJR_OK) return s;
+                        HJR_HIP(hipEventRecord(a, stream_));
+                    }
+                    HJR_HIP(launch_stage(prec != 0, d_insts_, prec ? d_tiles64_ : d_tiles32_, nt, stage, max_blocks_,
+                                         stream_));
+                    if (prof) HJR_HIP(hipEventRecord(b, stream_));
+                    ++launches_;
+                }
+            }
+            HJR_HIP(launch_step_end(d_insts_, ninst, stream_));
+            ++launches_;
+            if (any_interval_) {
+                HJR_HIP(launch_interval(false, d_insts_, d_tiles32_, n32_, max_blocks_, stream_));
+                HJR_HIP(launch_interval(true, d_insts_, d_tiles64_, n64_, max_blocks_, stream_));
+                HJR_HIP(launch_interval_end(d_insts_, ninst, stream_));
+                launches_ += 3;
+            }
+        }
+        ++chunks_;
+        HJR_HIP(hipMemcpyAsync(h_states_, d_states_, sizeof(SolveState) * ninst, hipMemcpyDeviceToHost, stream_));
+        HJR_HIP(hipStreamSynchronize(stream_));
+        if (prof && nev_ > 0) {
+            std::lock_guard<std::mutex> g(g_profile_mu);
+            for (int i = 0; i < nev_; ++i) {
+                EvRec &e = evs_[i];
+                float ms = 0.f;
+                HJR_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+                hjr_kernel_time &kt = e.prec ? g_profile.stage64[e.stage] : g_profile.stage32[e.stage];
+                kt.launches += 1;
+                kt.nodes += e.nodes;
+                kt.ms += ms;
+            }
+        }
+        return HJR_OK;
+    }
+
+    // Steps until the first running instance is expected to meet its threshold, from the decay
+    // of its max-change between the last two read-backs (geometric model); 0 if unknown.
+    int predict_steps()
+    {
+        double best = 0.0;
+        bool any = false;
+        for (int i = 0; i <= top_slot_; ++i) {
+            Request *r = slots_[i];
+            if (!r) continue;
+            const SolveState &st = h_states_[i];
+            Hist &h = hist_[i];
+            if (st.done != kRunning || st.phase != h.phase || st.n <= h.n || !(h.delta > 0.0)) {
+                h = Hist{st.phase, st.n, st.last_delta};
+                continue;
+            }
+            const double d = st.last_delta;
+            if (d > 0.0 && d < h.delta && st.tol > 0.0) {
+                const double rho = std::pow(d / h.delta, 1.0 / (double)(st.n - h.n));
+                const double rem = d <= st.tol ? 1.0 : std::log(st.tol / d) / std::log(rho);
+                if (!any || rem < best) best = rem;
+                any = true;
+            }
+            h = Hist{st.phase, st.n, st.last_delta};
+        }
+        if (!any) return 0;
+        return (int)std::min(1e6, std::ceil(best));
+    }
+
+    // Advance the phase machine of every instance after a chunk.  Finished requests are
+    // appended to `finished` (their slots are freed).
+    hjr_status update(std::vector<Request *> &finished)
+    {
+        for (int i = 0; i <= top_slot_; ++i) {
+            Request *r = slots_[i];
+            if (!r) continue;
+            const SolveState &st = h_states_[i];
+            if (st.done == kRunning) continue;
+            if (st.done == kNonFinite) {
+                r->status = fail(HJR_ERR_NONFINITE, "l or k holds a NaN or an infinity");
+                finish(r, finished, false);
+                continue;
+            }
+            const bool polish = r->phase == 0 && r->opts.precision == HJR_FP32_POLISH64 && st.done != kHorizon;
+            if (polish) {
+                r->iters0 = st.n;
+                r->phase = 1;
+                HJR_HIP(launch_polish(d_insts_, i, (uint32_t)r->npts, st.parity, r->opts.polish_shift, stream_));
+                h_states_[i].done = kRunning;  // until the next read-back
+                dirty_ = true;
+                continue;
+            }
+            // final phase done
+            hjr_result &res = r->result;
+            std::memset(&res, 0, sizeof res);
+            if (r->phase == 0) {
+                res.iterations = st.n;
+            } else {
+                res.iterations = r->iters0;
+                res.polish_iterations = st.n;
+            }
+            res.intervals = st.intervals;
+            res.t_final = st.t;
+            res.last_delta = st.last_delta;
+            res.dt = st.dt_nom;
+            res.max_abs_l = st.max_abs_l;
+            res.converged = st.done == kConverged ? 1 : (st.done == kHorizon ? 2 : 0);
+            r->status = st.done == kConverged ? HJR_OK : (st.done == kHorizon ? HJR_HORIZON : HJR_NOT_CONVERGED);
+            const bool from32 = r->phase == 0 && r->fp32_first;
+            const int parity = (r->opts.temporal == HJR_EULER) ? st.parity : 0;
+            if (from32 || parity) {
+                HJR_HIP(launch_output(d_insts_, i, (uint32_t)r->npts, from32, parity, r->V_dev, stream_));
+            }
+            finish(r, finished, true);
+        }
+        return HJR_OK;
+    }
+
+    // Free the slot of a finished request (its output stays in V_dev).
+    void finish(Request *r, std::vector<Request *> &finished, bool ok)
+    {
+        (void)ok;
+        const int i = r->slot;
+        h_states_[i].done = 99;
+        (void)hipMemcpyAsync(d_states_ + i, &h_states_[i], sizeof(SolveState), hipMemcpyHostToDevice, stream_);
+        slots_[i] = nullptr;
+        --nactive_;
+        r->result.seconds = now_s() - r->t_start;
+        finished.push_back(r);
+        dirty_ = true;
+    }
+
+    // Return a request's working memory to the pool (after its output has been consumed).
+    void drop(Request *r)
+    {
+        if (r->mem) Pool::get().release(r->mem);
+        r->mem = nullptr;
+    }
+
+private:
+    struct EvRec {
+        hipEvent_t a, b;
+        int prec, stage;
+        int64_t nodes;
+    };
+    struct Hist {
+        int phase = -1;
+        long long n = 0;
+        double delta = 0.0;
+    };
+
+    hjr_status event_pair(hipEvent_t *a, hipEvent_t *b, int prec, int stage, int64_t nodes)
+    {
+        if (nev_ == (int)evs_.size()) {
+            EvRec e{};
+            HJR_HIP(hipEventCreate(&e.a));
+            HJR_HIP(hipEventCreate(&e.b));
+            evs_.push_back(e);
+        }
+        EvRec &e = evs_[nev_++];
+        e.prec = prec;
+        e.stage = stage;
+        e.nodes = nodes;
+        *a = e.a;
+        *b = e.b;
+        return HJR_OK;
+    }
+
+    hjr_status rebuild()
+    {
+        std::vector<Tile> t32, t64;
+        top_slot_ = -1;
+        max_stages_ = 1;
+        any_interval_ = false;
+        for (int i = 0; i < cap_; ++i) {
+            Request *r = slots_[i];
+            if (!r) continue;
+            top_slot_ = i;
+            if (r->opts.temporal == HJR_TVDRK3) max_stages_ = 3;
+            if (r->opts.conv_mode == HJR_CONV_PER_INTERVAL) any_interval_ = true;
+            const bool fp64 = !(r->phase == 0 && r->fp32_first);
+            auto &dst = fp64 ? t64 : t32;
+            for (uint64_t s = 0; s < r->npts; s += kBlock) dst.push_back(Tile{i, (uint32_t)s});
+        }
+        if (top_slot_ < 0) top_slot_ = 0;
+        n32_ = (int)t32.size();
+        n64_ = (int)t64.size();
+        const size_t need = (t32.size() + t64.size() + 2) * sizeof(Tile);
+        if (need > tiles_cap_) {
+            HJR_HIP(hipStreamSynchronize(stream_));
+            Pool::get().release(d_tiles32_);
+            Pool::get().release(d_tiles64_);
+            if (h_tiles_) (void)hipHostFree(h_tiles_);
+            tiles_cap_ = std::max(need * 2, (size_t)4096);
+            HJR_HIP(Pool::get().alloc((void **)&d_tiles32_, tiles_cap_));
+            HJR_HIP(Pool::get().alloc((void **)&d_tiles64_, tiles_cap_));
+            HJR_HIP(hipHostMalloc((void **)&h_tiles_, tiles_cap_ * 2, hipHostMallocDefault));
+        }
+        // staging is reused: earlier copies from it must have completed
+        HJR_HIP(hipStreamSynchronize(stream_));
+        std::memcpy(h_tiles_, t32.data(), t32.size() * sizeof(Tile));
+        std::memcpy((char *)h_tiles_ + tiles_cap_, t64.data(), t64.size() * sizeof(Tile));
+        if (n32_) HJR_HIP(hipMemcpyAsync(d_tiles32_, h_tiles_, n32_ * sizeof(Tile), hipMemcpyHostToDevice, stream_));
+        if (n64_)
+            HJR_HIP(hipMemcpyAsync(d_tiles64_, (char *)h_tiles_ + tiles_cap_, n64_ * sizeof(Tile),
+                                   hipMemcpyHostToDevice, stream_));
+        dirty_ = false;
+        return HJR_OK;
+    }
+
+    int cap_;
+    int device_ = 0;
+    int cus_ = 256;
+    hipStream_t stream_ = nullptr;
+    bool own_stream_ = false;
+    SolveState *d_states_ = nullptr, *h_states_ = nullptr;
+    Inst *d_insts_ = nullptr, *h_insts_ = nullptr;
+    Tile *d_tiles32_ = nullptr, *d_tiles64_ = nullptr;
+    Tile *h_tiles_ = nullptr;
+    size_t tiles_cap_ = 0;
+    int n32_ = 0, n64_ = 0;
+    int top_slot_ = 0, max_stages_ = 1;
+    bool any_interval_ = false;
+    bool dirty_ = true;
+    int max_blocks_ = 0;
+    std::vector<Request *> slots_;
+    std::vector<Hist> hist_;
+    std::vector<EvRec> evs_;
+    int nev_ = 0;
+    int nactive_ = 0;
+    int64_t launches_ = 0, chunks_ = 0;
+};
+
+// Chunk-size policy.  Every step launched after an instance has converged is a launch that
+// returns at once; to keep those few, the next chunk is sized from the predicted number of steps
+// to convergence, and otherwise grows geometrically while nothing finishes.
+struct ChunkPolicy {
+    int fixed, cur;
+    explicit ChunkPolicy(int steps_per_sync) : fixed(steps_per_sync), cur(steps_per_sync > 0 ? steps_per_sync : 4) {}
+    int next() const { return cur; }
+    void after(bool something_finished, int predicted)
+    {
+        if (fixed > 0) return;
+        int grow = something_finished ? 4 : std::min(cur * 2, 64);
+        if (predicted > 0) grow = std::max(1, std::min(grow, predicted));
+        cur = grow;
+    }
+};
+
+static hjr_status prepare(Request &r, const hjr_grid *g, const hjr_dynamics *dy, const hjr_options *o)
+{
+    hjr_status s = validate_opts(o);
+    if (s != HJR_OK) return s;
+    uint64_t N = 0;
+    s = validate(g, dy, o->spatial, &N);
+    if (s != HJR_OK) return s;
+    r.grid = *g;
+    r.dyn = *dy;
+    r.opts = *o;
+    r.npts = N;
+    return HJR_OK;
+}
+
+// Run a set of requests to completion on one engine (used by the synchronous entry points).
+static hjr_status run_all(Engine &E, std::vector<Request *> &reqs, bool own_io, const std::vector<const double *> &lh,
+                          const std::vector<const double *> &kh, int steps_per_sync)
+{
+    size_t next = 0;
+    ChunkPolicy pol(steps_per_sync);
+    std::vector<Request *> fin;
+    while (next < reqs.size() || E.active() > 0) {
+        while (next < reqs.size() && E.has_free_slot()) {
+            Request *r = reqs[next];
+            hjr_status s = E.admit(r, own_io, own_io ? lh[next] : nullptr, own_io ? kh[next] : nullptr);
+            if (s != HJR_OK) return s;
+            ++next;
+        }
+        hjr_status s = E.run_chunk(pol.next());
+        if (s != HJR_OK) return s;
+        const size_t before = fin.size();
+        s = E.update(fin);
+        if (s != HJR_OK) return s;
+        pol.after(fin.size() > before, E.predict_steps());
+    }
+    HJR_HIP(hipStreamSynchronize(E.stream()));
+    return HJR_OK;
+}
+
+}  // namespace hjr
+
+// ============================================================================================
+// C ABI
+// ============================================================================================
+
+using namespace hjr;
+
+extern "C" {
+
+int32_t hjr_abi_version(void) { return HJR_ABI_VERSION; }
+
+hjr_status hjr_default_options(hjr_options *o)
+{
+    if (!o) return fail(HJR_ERR_INVALID_ARG, "options must not be NULL");
+    std::memset(o, 0, sizeof *o);
+    o->game = HJR_AVOID;
+    o->spatial = HJR_WENO5;
+    o->temporal = HJR_TVDRK3;
+    o->precision = HJR_FP32_POLISH64;
+    o->conv_mode = HJR_CONV_PER_STEP;
+    o->steps_per_sync = 0;
+    o->cfl = 0.5;
+    o->tol = 1e-6;
+    o->tol_fp32 = 0.0;
+    o->polish_shift = -1.0;
+    o->dt_report = 0.01;
+    o->t_max = 0.0;
+    o->dt_max = 0.0;
+    o->max_iter = 1000000;
+    return HJR_OK;
+}
+
+const char *hjr_status_string(hjr_status s)
+{
+    switch (s) {
+    case HJR_OK: return "ok";
+    case HJR_NOT_CONVERGED: return "not converged (max_iter reached)";
+    case HJR_PENDING: return "pending";
+    case HJR_HORIZON: return "horizon reached";
+    case HJR_ERR_INVALID_ARG: return "invalid argument";
+    case HJR_ERR_UNSUPPORTED: return "unsupported";
+    case HJR_ERR_NONFINITE: return "non-finite input";
+    case HJR_ERR_OOM: return "out of device memory";
+    case HJR_ERR_DEVICE: return "device error";
+    case HJR_ERR_BUDGET: return "request exceeds the memory budget";
+    case HJR_ERR_UNKNOWN_TICKET: return "unknown ticket";
+    default: return "unknown status";
+    }
+}
+
+const char *hjr_last_error(void) { return g_last_error.c_str(); }
+
+int32_t hjr_device_count(void)
+{
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
+hjr_status hjr_solve(const hjr_grid *grid, const hjr_dynamics *dyn, const double *l, const double *k,
+                     const hjr_options *opts, double *V_out, hjr_result *result)
+{
+    Request r;
+    hjr_status s = prepare(r, grid, dyn, opts);
+    if (s != HJR_OK) return s;
+    if (!l || !V_out) return fail(HJR_ERR_INVALID_ARG, "l and V_out must not be NULL");
+    Engine E(1);
+    s = E.init(nullptr);
+    if (s != HJR_OK) return s;
+    std::vector<Request *> reqs{&r};
+    s = run_all(E, reqs, true, {l}, {k}, opts->steps_per_sync);
+    if (s == HJR_OK && r.status >= 0) {
+        hipError_t e = hipMemcpy(V_out, r.V_dev, r.npts * 8, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) s = fail(HJR_ERR_DEVICE, "copy of V failed: %s", hipGetErrorString(e));
+    }
+    E.drop(&r);
+    if (s != HJR_OK) return s;
+    if (result) *result = r.result;
+    return r.status;
+}
+
+hjr_status hjr_solve_device(const hjr_grid *grid, const hjr_dynamics *dyn, const double *l_dev, const double *k_dev,
+                            const hjr_options *opts, double *V_dev, void *stream, hjr_result *result)
+{
+    Request r;
+    hjr_status s = prepare(r, grid, dyn, opts);
+    if (s != HJR_OK) return s;
+    if (!l_dev || !V_dev) return fail(HJR_ERR_INVALID_ARG, "l_dev and V_dev must not be NULL");
+    r.l_dev = l_dev;
+    r.k_dev = k_dev;
+    r.V_dev = V_dev;
+    Engine E(1);
+    s = E.init((hipStream_t)stream);
+    if (s != HJR_OK) return s;
+    std::vector<Request *> reqs{&r};
+    s = run_all(E, reqs, false, {}, {}, opts->steps_per_sync);
+    E.drop(&r);
+    if (s != HJR_OK) return s;
+    if (result) *result = r.result;
+    return r.status;
+}
+
+hjr_status hjr_batch_solve(int32_t count, hjr_problem *problems)
+{
+    if (count < 0 || (count > 0 && !problems)) return fail(HJR_ERR_INVALID_ARG, "bad problem list");
+    if (count == 0) return HJR_OK;
+    std::vector<Request> rs(count);
+    std::vector<Request *> reqs;
+    std::vector<const double *> lh, kh;
+    int sps = 0;
+    for (int i = 0; i < count; ++i) {
+        hjr_problem &p = problems[i];
+        hjr_status s = prepare(rs[i], &p.grid, &p.dyn, &p.opts);
+        if (s == HJR_OK && (!p.l || !p.V_out)) s = fail(HJR_ERR_INVALID_ARG, "problem %d: NULL array", i);
+        if (s != HJR_OK) {
+            p.status = s;
+            return fail(s, "problem %d: %s", i, g_last_error.c_str());
+        }
+        reqs.push_back(&rs[i]);
+        lh.push_back(p.l);
+        kh.push_back(p.k);
+        sps = std::max(sps, p.opts.steps_per_sync);
+    }
+    Engine E(count);
+    hjr_status s = E.init(nullptr);
+    if (s != HJR_OK) return s;
+    s = run_all(E, reqs, true, lh, kh, sps);
+    hjr_status first = HJR_OK;
+    for (int i = 0; i < count; ++i) {
+        Request &r = rs[i];
+        if (s == HJR_OK && r.status >= 0) {
+            hipError_t e = hipMemcpy(problems[i].V_out, r.V_dev, r.npts * 8, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) r.status = fail(HJR_ERR_DEVICE, "copy failed: %s", hipGetErrorString(e));
+        }
+        problems[i].status = s == HJR_OK ? r.status : s;
+        problems[i].result = r.result;
+        if (first == HJR_OK && problems[i].status != HJR_OK) first = problems[i].status;
+        E.drop(&r);
+    }
+    return s != HJR_OK ? s : first;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Kernel timing
+// ---------------------------------------------------------------------------------------------
+
+hjr_status hjr_profile_enable(int32_t on)
+{
+    g_profile_on.store(on ? 1 : 0);
+    return HJR_OK;
+}
+
+hjr_status hjr_profile_read(hjr_profile *out, int32_t reset)
+{
+    std::lock_guard<std::mutex> g(g_profile_mu);
+    if (out) *out = g_profile;
+    if (reset) std::memset(&g_profile, 0, sizeof g_profile);
+    return HJR_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Kernel-level entry points
+// ---------------------------------------------------------------------------------------------
+
+hjr_status hjr_cfl_dt(const hjr_grid *grid, const hjr_dynamics *dyn, double cfl, double dt_max, double *dt_out)
+{
+    if (!dt_out) return fail(HJR_ERR_INVALID_ARG, "dt_out must not be NULL");
+    hjr_options o;
+    hjr_default_options(&o);
+    o.spatial = HJR_UPWIND1;
+    o.precision = HJR_FP64;
+    o.cfl = cfl;
+    o.dt_max = dt_max;
+    Request r;
+    hjr_status s = prepare(r, grid, dyn, &o);
+    if (s != HJR_OK) return s;
+    std::vector<double> zeros(r.npts, 0.0);
+    Engine E(1);
+    s = E.init(nullptr);
+    if (s != HJR_OK) return s;
+    s = E.admit(&r, true, zeros.data(), nullptr);
+    if (s == HJR_OK) {
+        SolveState st;
+        hipError_t e = hipStreamSynchronize(E.stream());
+        if (e == hipSuccess) e = hipMemcpy(&st, r.inst.state, sizeof st, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) s = fail(HJR_ERR_DEVICE, "state copy failed: %s", hipGetErrorString(e));
+        else *dt_out = st.dt_nom;
+    }
+    std::vector<Request *> fin;
+    E.finish(&r, fin, false);
+    (void)hipStreamSynchronize(E.stream());
+    E.drop(&r);
+    return s;
+}
+
+hjr_status hjr_stage_device(const hjr_grid *grid, const hjr_dynamics *dyn, int32_t game, int32_t spatial,
+                            int32_t temporal, int32_t stage, int32_t precision, double dt, const void *Vs,
+                            const void *Vn, const void *l, void *out, double *delta_out, void *stream)
+{
+    hjr_options o;
+    hjr_default_options(&o);
+    o.game = game;
+    o.spatial = spatial;
+    o.temporal = temporal;
+    o.precision = precision == HJR_FP32 ? HJR_FP32 : HJR_FP64;
+    Request r;
+    hjr_status s = prepare(r, grid, dyn, &o);
+    if (s != HJR_OK) return s;
+    const int nst = temporal == HJR_TVDRK3 ? 3 : 1;
+    if (stage < 1 || stage > nst) return fail(HJR_ERR_INVALID_ARG, "stage %d out of range 1..%d", stage, nst);
+    if (!Vs || !Vn || !l || !out) return fail(HJR_ERR_INVALID_ARG, "NULL array");
+    if (out == Vs) return fail(HJR_ERR_INVALID_ARG, "out must not alias Vs");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HJR_ERR_INVALID_ARG, "dt must be > 0");
+    hipStream_t st = (hipStream_t)stream;
+    const bool f32 = precision == HJR_FP32;
+    const size_t esz = f32 ? 4 : 8;
+    // descriptor with the caller's arrays in the roles the kernel expects for this stage
+    Layout L = plan_layout(r, false);
+    void *mem = nullptr;
+    HJR_HIP(Pool::get().alloc(&mem, L.total + align256(sizeof(SolveState)) + align256(sizeof(Inst))));
+    char *base = (char *)mem;
+    SolveState *dstate = (SolveState *)(base + align256(L.total));
+    Inst *dinst = (Inst *)((char *)dstate + align256(sizeof(SolveState)));
+    std::vector<double> t64;
+    std::vector<float> t32;
+    build_inst(r, base, L, t64, t32, dstate);
+    Inst I = r.inst;
+    void *Vfield = (void *)Vn, *Afield = nullptr, *Bfield = nullptr;
+    const int k = stage - 1;
+    hipError_t e = hipSuccess;
+    if (temporal == HJR_EULER) {
+        Vfield = (void *)Vs;
+        Afield = out;
+    } else if (k == 0) {
+        Vfield = (void *)Vs;
+        Afield = out;
+    } else if (k == 1) {
+        Vfield = (void *)Vn;
+        Afield = (void *)Vs;
+        Bfield = out;
+    } else {
+        e = hipMemcpyAsync(out, Vn, r.npts * esz, hipMemcpyDeviceToDevice, st);
+        Vfield = out;
+        Bfield = (void *)Vs;
+    }
+    if (f32) {
+        I.V32 = (float *)Vfield;
+        I.A32 = (float *)Afield;
+        I.B32 = (float *)Bfield;
+        I.l32 = (const float *)l;
+    } else {
+        I.V64 = (double *)Vfield;
+        I.A64 = (double *)Afield;
+        I.B64 = (double *)Bfield;
+        I.l64 = (const double *)l;
+    }
+    SolveState hs = initial_state(r);
+    hs.dt_cur = dt;
+    hs.dt_nom = dt;
+    hs.done = kRunning;
+    std::vector<Tile> tiles;
+    for (uint64_t s0 = 0; s0 < r.npts; s0 += kBlock) tiles.push_back(Tile{0, (uint32_t)s0});
+    void *dtl = nullptr;
+    if (e == hipSuccess) e = Pool::get().alloc(&dtl, tiles.size() * sizeof(Tile));
+    if (e == hipSuccess) e = hipMemcpyAsync((void *)I.tab64, t64.data(), t64.size() * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync((void *)I.tab32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dstate, &hs, sizeof hs, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dinst, &I, sizeof I, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dtl, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_stage(!f32, dinst, (const Tile *)dtl, (int)tiles.size(), k, 0, st);
+    SolveState after;
+    if (e == hipSuccess) e = hipMemcpyAsync(&after, dstate, sizeof after, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    Pool::get().release(dtl);
+    Pool::get().release(mem);
+    if (e != hipSuccess) return fail(HJR_ERR_DEVICE, "stage launch failed: %s", hipGetErrorString(e));
+    const bool last = temporal == HJR_EULER || k == 2;
+    if (delta_out && last) *delta_out = __builtin_bit_cast(double, after.delta_bits);
+    return HJR_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================================
+// Serving context
+// ============================================================================================
+
+struct hjr_ctx {
+    int device = 0;
+    size_t budget = 0;
+    std::unique_ptr<Engine> engine;
+    std::mutex mu;
+    std::condition_variable cv, cv_done;
+    std::deque<Request *> queue;
+    std::unordered_map<int64_t, std::unique_ptr<Request>> all;
+    int64_t next_ticket = 1;
+    size_t in_use = 0, peak = 0;
+    int64_t admitted = 0, finished = 0;
+    bool stop = false;
+    hjr_status fatal = HJR_OK;
+    std::string fatal_msg;
+    std::thread worker;
+    int steps_per_chunk = 4;
+
+    void loop()
+    {
+        (void)hipSetDevice(device);
+        std::vector<Request *> fin;
+        while (true) {
+            {
+                std::unique_lock<std::mutex> g(mu);
+                cv.wait(g, [&] { return stop || !queue.empty() || engine->active() > 0; });
+                if (stop && queue.empty() && engine->active() == 0) return;
+                // admit in arrival order while memory and slots allow
+                while (!queue.empty() && engine->has_free_slot()) {
+                    Request *r = queue.front();
+                    const size_t b = request_bytes(*r, false);
+                    if (in_use + b > budget) break;
+                    queue.pop_front();
+                    in_use += b;
+                    peak = std::max(peak, in_use);
+                    g.unlock();
+                    hjr_status s = engine->admit(r, false, nullptr, nullptr);
+                    g.lock();
+                    ++admitted;
+                    if (s != HJR_OK) {
+                        r->status = s;
+                        r->done = true;
+                        in_use -= b;
+                        cv_done.notify_all();
+                    }
+                }
+            }
+            if (engine->active() == 0) continue;
+            hjr_status s = engine->run_chunk(steps_per_chunk);
+            fin.clear();
+            if (s == HJR_OK) s = engine->update(fin);
+            if (s == HJR_OK && !fin.empty()) {
+                hipError_t e = hipStreamSynchronize(engine->stream());
+                if (e != hipSuccess) s = fail(HJR_ERR_DEVICE, "sync failed: %s", hipGetErrorString(e));
+            }
+            std::lock_guard<std::mutex> g(mu);
+            if (s != HJR_OK) {
+                fatal = s;
+                fatal_msg = g_last_error;
+                for (auto &kv : all)
+                    if (!kv.second->done) {
+                        kv.second->status = s;
+                        kv.second->done = true;
+                    }
+                queue.clear();
+                cv_done.notify_all();
+                return;
+            }
+            for (Request *r : fin) {
+                in_use -= r->bytes;
+                engine->drop(r);
+                r->done = true;
+                ++finished;
+            }
+            if (!fin.empty()) cv_done.notify_all();
+        }
+    }
+};
+
+extern "C" {
+
+hjr_status hjr_ctx_create(int32_t device, size_t hbm_budget_bytes, hjr_ctx **out)
+{
+    if (!out) return fail(HJR_ERR_INVALID_ARG, "out must not be NULL");
+    int n = 0;
+    HJR_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(HJR_ERR_INVALID_ARG, "device %d out of range", device);
+    HJR_HIP(hipSetDevice(device));
+    auto c = std::make_unique<hjr_ctx>();
+    c->device = device;
+    size_t fr = 0, tot = 0;
+    HJR_HIP(hipMemGetInfo(&fr, &tot));
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
+    c->engine = std::make_unique<Engine>(256);
+    hjr_status s = c->engine->init(nullptr);
+    if (s != HJR_OK) return s;
+    hjr_ctx *p = c.release();
+    p->worker = std::thread([p] { p->loop(); });
+    *out = p;
+    return HJR_OK;
+}
+
+hjr_status hjr_submit(hjr_ctx *ctx, const hjr_grid *grid, const hjr_dynamics *dyn, const double *l_dev,
+                      const double *k_dev, const hjr_options *opts, double *V_dev, int64_t *ticket)
+{
+    if (!ctx || !ticket) return fail(HJR_ERR_INVALID_ARG, "ctx and ticket must not be NULL");
+    auto r = std::make_unique<Request>();
+    hjr_status s = prepare(*r, grid, dyn, opts);
+    if (s != HJR_OK) return s;
+    if (!l_dev || !V_dev) return fail(HJR_ERR_INVALID_ARG, "l_dev and V_dev must not be NULL");
+    r->l_dev = l_dev;
+    r->k_dev = k_dev;
+    r->V_dev = V_dev;
+    if (request_bytes(*r, false) > ctx->budget)
+        return fail(HJR_ERR_BUDGET, "request needs %zu bytes, budget is %zu", request_bytes(*r, false), ctx->budget);
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (ctx->fatal != HJR_OK) return fail(ctx->fatal, "context failed: %s", ctx->fatal_msg.c_str());
+    r->ticket = ctx->next_ticket++;
+    r->t_submit = now_s();
+    *ticket = r->ticket;
+    ctx->queue.push_back(r.get());
+    ctx->all[r->ticket] = std::move(r);
+    ctx->cv.notify_all();
+    return HJR_OK;
+}
+
+hjr_status hjr_poll(hjr_ctx *ctx, int64_t ticket, hjr_result *result)
+{
+    if (!ctx) return fail(HJR_ERR_INVALID_ARG, "ctx must not be NULL");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    auto it = ctx->all.find(ticket);
+    if (it == ctx->all.end()) return fail(HJR_ERR_UNKNOWN_TICKET, "unknown ticket %lld", (long long)ticket);
+    Request *r = it->second.get();
+    if (!r->done) return HJR_PENDING;
+    hjr_status s = r->status;
+    if (result) *result = r->result;
+    if (s < 0) fail(s, "request %lld failed", (long long)ticket);
+    ctx->all.erase(it);
+    return s;
+}
+
+hjr_status hjr_ctx_drain(hjr_ctx *ctx)
+{
+    if (!ctx) return fail(HJR_ERR_INVALID_ARG, "ctx must not be NULL");
+    std::unique_lock<std::mutex> g(ctx->mu);
+    ctx->cv_done.wait(g, [&] {
+        for (auto &kv : ctx->all)
+            if (!kv.second->done) return false;
+        return true;
+    });
+    return ctx->fatal;
+}
+
+hjr_status hjr_ctx_get_stats(hjr_ctx *ctx, hjr_ctx_stats *st)
+{
+    if (!ctx || !st) return fail(HJR_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    st->admitted = ctx->admitted;
+    st->finished = ctx->finished;
+    st->queued = (int64_t)ctx->queue.size();
+    st->running = ctx->engine->active();
+    st->bytes_in_use = (int64_t)ctx->in_use;
+    st->bytes_peak = (int64_t)ctx->peak;
+    st->budget = (int64_t)ctx->budget;
+    st->chunks = ctx->engine->chunks();
+    st->launches = ctx->engine->launches();
+    return HJR_OK;
+}
+
+hjr_status hjr_ctx_destroy(hjr_ctx *ctx)
+{
+    if (!ctx) return HJR_OK;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->stop = true;
+        ctx->queue.clear();
+        ctx->cv.notify_all();
+    }
+    if (ctx->worker.joinable()) ctx->worker.join();
+    hjr_status s = ctx->fatal;
+    delete ctx;
+    return s;
+}
+
+}  // extern "C"

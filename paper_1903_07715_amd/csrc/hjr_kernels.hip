@@ -1,0 +1,453 @@
+// hjr_kernels.hip -- gfx950 kernels of the HJI VI grid update and their launch wrappers.
+//
+// Work is described by a list of tiles (instance, first node); a tile is kBlock consecutive
+// nodes of one instance's flattened grid.  One launch of a stage kernel advances every tile of
+// every instance in its list, so a batch of grids of different size and dimension moves in one
+// launch per stage.  Workgroups are mapped to tiles so that each XCD (workgroups are dealt to
+// the eight XCDs round-robin) takes one contiguous run of tiles: the stencil halo of a tile is
+// then mostly in the same XCD's L2.  A grid smaller than the tile count makes each workgroup
+// loop over its XCD's run (persistent mode).
+#include "hjr_kernels.hpp"
+
+namespace hjr {
+
+// --------------------------------------------------------------------------------------------
+// Reductions
+// --------------------------------------------------------------------------------------------
+
+// max that propagates NaN (fmax would drop it and let a blown-up field look converged)
+__device__ __forceinline__ double nanmax(double a, double b) { return (a != a || a > b) ? a : b; }
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ unsigned wave_sum(unsigned v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block-wide max of a non-negative value, then one atomic max into *dst (FP64 bits).
+__device__ __forceinline__ void block_max_to(double v, unsigned long long *dst, double *red)
+{
+    v = wave_max(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+#pragma unroll
+        for (int w = 1; w < kBlock / 64; ++w) m = nanmax(m, red[w]);
+        if (m > 0.0 || m != m) atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+    }
+    __syncthreads();
+}
+
+// --------------------------------------------------------------------------------------------
+// Tile mapping
+// --------------------------------------------------------------------------------------------
+
+struct TileRange {
+    int first, count, step;
+};
+
+__device__ __forceinline__ TileRange xcd_range(int ntiles)
+{
+    // X groups of workgroups: with 8 or more workgroups, group x is the workgroups that land on
+    // XCD x; each group owns one contiguous run of tiles and deals it out round-robin.
+    const int G = gridDim.x, b = blockIdx.x;
+    const int X = G < 8 ? G : 8;
+    const int x = b % X, k = b / X;
+    const int bx = G / X + (x < G % X ? 1 : 0);            // workgroups in group x
+    const int tn = ntiles / X + (x < ntiles % X ? 1 : 0);  // tiles of group x
+    const int t0 = x * (ntiles / X) + min(x, ntiles % X);
+    TileRange r;
+    r.first = t0 + k;
+    r.count = k < tn ? (tn - k + bx - 1) / bx : 0;
+    r.step = bx;
+    return r;
+}
+
+// --------------------------------------------------------------------------------------------
+// Stage kernel
+// --------------------------------------------------------------------------------------------
+
+template <typename T, int DYN, int SPATIAL>
+__device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int stage, T dt, double *red)
+{
+    using F = Fields<T>;
+    SolveState *st = I.state;
+    const bool euler = I.temporal == kEuler;
+    const int par = euler ? st->parity : 0;
+    T *V = F::V(I), *A = F::A(I), *B = F::B(I);
+    const T *S, *Vn;
+    T *O;
+    if (euler) {
+        S = par ? A : V;
+        Vn = S;
+        O = par ? V : A;
+    } else if (stage == 0) {
+        S = V; Vn = V; O = A;
+    } else if (stage == 1) {
+        S = A; Vn = V; O = B;
+    } else {
+        S = B; Vn = V; O = V;
+    }
+    const bool last = euler || stage == 2;
+    const uint32_t node = start + threadIdx.x;
+    double delta = 0.0;
+    if (node < I.npts) {
+        T L = lf_operator<T, DYN, SPATIAL>(I, S, node);
+        T s = S[node];
+        T vn = Vn[node];
+        T out;
+        if (euler) {
+            out = fmin(F::l(I)[node], s + dt * L);
+        } else if (stage == 0) {
+            out = s + dt * L;
+        } else if (stage == 1) {
+            out = T(0.75) * vn + T(0.25) * (s + dt * L);
+        } else {
+            out = fmin(F::l(I)[node], vn * T(1.0 / 3.0) + T(2.0 / 3.0) * (s + dt * L));
+        }
+        O[node] = out;
+        if (last) delta = (double)fabs(out - vn);
+    }
+    if (last) block_max_to(delta, &st->delta_bits, red);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void stage_kernel(const Inst *__restrict__ insts,
+                                                       const Tile *__restrict__ tiles, int ntiles,
+                                                       int stage)
+{
+    __shared__ double red[kBlock / 64];
+    const TileRange r = xcd_range(ntiles);
+    for (int c = 0; c < r.count; ++c) {
+        const Tile tl = tiles[r.first + c * r.step];
+        const Inst &I = insts[tl.inst];
+        SolveState *st = I.state;
+        if (st->done != kRunning || stage >= I.nstages) continue;
+        const T dt = (T)st->dt_cur;
+        const int key = I.dyn * 8 + I.spatial;
+        switch (key) {
+        case kDynDI * 8 + kUpwind1: stage_tile<T, kDynDI, kUpwind1>(I, tl.start, stage, dt, red); break;
+        case kDynDI * 8 + kWeno5: stage_tile<T, kDynDI, kWeno5>(I, tl.start, stage, dt, red); break;
+        case kDynDubins * 8 + kUpwind1: stage_tile<T, kDynDubins, kUpwind1>(I, tl.start, stage, dt, red); break;
+        case kDynDubins * 8 + kWeno5: stage_tile<T, kDynDubins, kWeno5>(I, tl.start, stage, dt, red); break;
+        case kDynUnicycle * 8 + kUpwind1: stage_tile<T, kDynUnicycle, kUpwind1>(I, tl.start, stage, dt, red); break;
+        case kDynUnicycle * 8 + kWeno5: stage_tile<T, kDynUnicycle, kWeno5>(I, tl.start, stage, dt, red); break;
+        case kDynQuad * 8 + kUpwind1: stage_tile<T, kDynQuad, kUpwind1>(I, tl.start, stage, dt, red); break;
+        case kDynQuad * 8 + kWeno5: stage_tile<T, kDynQuad, kWeno5>(I, tl.start, stage, dt, red); break;
+        default: break;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// Step bookkeeping (one thread per instance)
+// --------------------------------------------------------------------------------------------
+
+// Step size for the next step: the CFL step, cut so the step ends exactly at t_max and, in
+// interval mode, at the end of the current report interval.
+__device__ __forceinline__ double next_dt(const SolveState *st)
+{
+    double dt = st->dt_nom;
+    if (st->t_max > 0.0 && st->t_max - st->t < dt) dt = st->t_max - st->t;
+    if (st->conv_mode == 1 && st->dt_report - st->t_int < dt) dt = st->dt_report - st->t_int;
+    return dt;
+}
+
+__device__ __forceinline__ void apply_limits(SolveState *st)
+{
+    if (st->done != kRunning) return;
+    if (st->max_iter > 0 && st->n >= st->max_iter) {
+        st->done = kMaxIter;
+    } else if (st->t_max > 0.0 && st->t >= st->t_max * (1.0 - 1e-12)) {
+        st->done = kHorizon;
+    } else {
+        st->dt_cur = next_dt(st);
+    }
+}
+
+__global__ void step_end_kernel(const Inst *__restrict__ insts, int ninst)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst) return;
+    const Inst &I = insts[i];
+    SolveState *st = I.state;
+    if (st->done != kRunning) return;
+    const double dt = st->dt_cur;
+    st->n += 1;
+    st->t += dt;
+    const double delta = __longlong_as_double((long long)st->delta_bits);
+    st->delta_bits = 0ull;
+    if (I.temporal == kEuler) st->parity ^= 1;
+    if (st->conv_mode == 0) {
+        st->last_delta = delta;
+        if (delta < st->tol) st->done = kConverged;
+        apply_limits(st);
+    } else {
+        st->t_int += dt;
+        st->check_interval = st->t_int >= st->dt_report * (1.0 - 1e-12) ? 1 : 0;
+        if (!st->check_interval) apply_limits(st);
+    }
+}
+
+// Interval mode: change across the interval that just closed, and new snapshot.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void interval_kernel(const Inst *__restrict__ insts,
+                                                          const Tile *__restrict__ tiles, int ntiles)
+{
+    using F = Fields<T>;
+    __shared__ double red[kBlock / 64];
+    const TileRange r = xcd_range(ntiles);
+    for (int c = 0; c < r.count; ++c) {
+        const Tile tl = tiles[r.first + c * r.step];
+        const Inst &I = insts[tl.inst];
+        SolveState *st = I.state;
+        if (st->done != kRunning || !st->check_interval) continue;
+        const T *cur = (I.temporal == kEuler && st->parity) ? F::A(I) : F::V(I);
+        T *snap = F::snap(I);
+        const uint32_t node = tl.start + threadIdx.x;
+        double d = 0.0;
+        if (node < I.npts) {
+            T v = cur[node];
+            d = (double)fabs(v - snap[node]);
+            snap[node] = v;
+        }
+        block_max_to(d, &st->idelta_bits, red);
+    }
+}
+
+__global__ void interval_end_kernel(const Inst *__restrict__ insts, int ninst)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst) return;
+    SolveState *st = insts[i].state;
+    if (st->done != kRunning || !st->check_interval) return;
+    const double d = __longlong_as_double((long long)st->idelta_bits);
+    st->idelta_bits = 0ull;
+    st->check_interval = 0;
+    st->intervals += 1;
+    st->t_int = 0.0;
+    st->last_delta = d;
+    if (d < st->tol) st->done = kConverged;
+    apply_limits(st);
+}
+
+// --------------------------------------------------------------------------------------------
+// Solve set-up: initial value, input checks, max |l|, CFL rate (one pass over the grid)
+// --------------------------------------------------------------------------------------------
+
+template <int DYN>
+__device__ __forceinline__ double rate_of(const Inst &I, uint32_t node) { return cfl_rate<DYN>(I, node); }
+
+__global__ __launch_bounds__(kBlock) void init_kernel(const Inst *__restrict__ insts, int inst,
+                                                      const double *__restrict__ l64,
+                                                      const double *__restrict__ k64, int fp32)
+{
+    __shared__ double red[kBlock / 64];
+    __shared__ unsigned cnt[kBlock / 64];
+    const Inst &I = insts[inst];
+    SolveState *st = I.state;
+    const uint32_t node = blockIdx.x * kBlock + threadIdx.x;
+    double lmax = 0.0, rate = 0.0;
+    unsigned bad = 0;
+    if (node < I.npts) {
+        double l = l64[node];
+        double v = l;
+        bad = isfinite(l) ? 0u : 1u;
+        if (k64) {
+            double k = k64[node];
+            bad |= isfinite(k) ? 0u : 1u;
+            v = k < l ? k : l;
+        }
+        lmax = fabs(l);
+        if (fp32) {
+            I.V32[node] = (float)v;
+            const_cast<float *>(I.l32)[node] = (float)l;
+            if (I.Vs32) I.Vs32[node] = (float)v;
+        } else {
+            I.V64[node] = v;
+            if (I.Vs64) I.Vs64[node] = v;
+        }
+        switch (I.dyn) {
+        case kDynDI: rate = rate_of<kDynDI>(I, node); break;
+        case kDynDubins: rate = rate_of<kDynDubins>(I, node); break;
+        case kDynUnicycle: rate = rate_of<kDynUnicycle>(I, node); break;
+        default: rate = rate_of<kDynQuad>(I, node); break;
+        }
+    }
+    unsigned b = wave_sum(bad);
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = b;
+    block_max_to(lmax, &st->lmax_bits, red);
+    block_max_to(rate, &st->rate_bits, red);
+    if (threadIdx.x == 0) {
+        unsigned s = 0;
+        for (int w = 0; w < kBlock / 64; ++w) s += cnt[w];
+        if (s) atomicAdd(&st->nonfinite, s);
+    }
+}
+
+// dt, phase threshold and first step size, after init_kernel.
+__global__ void setup_kernel(const Inst *__restrict__ insts, int inst, int fp32_phase)
+{
+    if (threadIdx.x != 0) return;
+    SolveState *st = insts[inst].state;
+    const double rate = __longlong_as_double((long long)st->rate_bits);
+    st->max_abs_l = __longlong_as_double((long long)st->lmax_bits);
+    double dt = rate > 0.0 ? st->cfl / rate : 1.0;
+    if (st->dt_max > 0.0 && dt > st->dt_max) dt = st->dt_max;
+    st->dt_nom = dt;
+    double tol = st->tol_final;
+    if (fp32_phase) {
+        if (st->tol32_req > 0.0) {
+            tol = st->tol32_req;
+        } else if (st->max_abs_l > 0.0) {
+            int e;
+            (void)frexp(st->max_abs_l, &e);
+            const double ulp = ldexp(1.0, e - 24);  // FP32 spacing at max |l|
+            tol = fmax(tol, 8.0 * ulp);
+        }
+    }
+    st->tol = tol;
+    st->done = st->nonfinite ? kNonFinite : kRunning;
+    st->dt_cur = next_dt(st);
+    if (st->max_iter > 0 && st->n >= st->max_iter) st->done = kMaxIter;
+}
+
+// --------------------------------------------------------------------------------------------
+// FP32 -> FP64 polish hand-over and result extraction
+// --------------------------------------------------------------------------------------------
+
+// Reset the per-phase counters for the polish; remembers where the FP32 iterate is.
+__global__ void polish_switch_kernel(const Inst *__restrict__ insts, int inst, double shift_req)
+{
+    if (threadIdx.x != 0) return;
+    SolveState *st = insts[inst].state;
+    st->tol32_req = shift_req >= 0.0 ? shift_req : 2.0 * st->tol;  // reused: the shift
+    st->phase = 1;
+    st->parity = 0;
+    st->done = kRunning;
+    st->n = 0;
+    st->delta_bits = 0ull;
+    st->idelta_bits = 0ull;
+    st->check_interval = 0;
+    st->t_int = 0.0;
+    st->tol = st->tol_final;
+    st->dt_cur = next_dt(st);
+}
+
+__global__ __launch_bounds__(kBlock) void polish_init_kernel(const Inst *__restrict__ insts, int inst,
+                                                             int parity32)
+{
+    const Inst &I = insts[inst];
+    const uint32_t node = blockIdx.x * kBlock + threadIdx.x;
+    if (node >= I.npts) return;
+    const float *cur = parity32 ? I.A32 : I.V32;
+    const double shift = I.state->tol32_req;
+    const double l = I.l64[node];
+    const double v = (double)cur[node] + shift;
+    const double v0 = v < l ? v : l;
+    I.V64[node] = v0;
+    if (I.Vs64) I.Vs64[node] = v0;
+}
+
+// Final iterate into the FP64 output array.
+__global__ __launch_bounds__(kBlock) void output_kernel(const Inst *__restrict__ insts, int inst,
+                                                        int from32, int parity, double *out)
+{
+    const Inst &I = insts[inst];
+    const uint32_t node = blockIdx.x * kBlock + threadIdx.x;
+    if (node >= I.npts) return;
+    if (from32) {
+        const float *cur = parity ? I.A32 : I.V32;
+        out[node] = (double)cur[node];
+    } else {
+        out[node] = parity ? I.A64[node] : I.V64[node];
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// Launch wrappers
+// --------------------------------------------------------------------------------------------
+
+static inline int grid_for(int ntiles, int max_blocks)
+{
+    if (max_blocks > 0 && ntiles > max_blocks) return max_blocks;
+    return ntiles;
+}
+
+hipError_t launch_stage(bool fp64, const Inst *insts, const Tile *tiles, int ntiles, int stage,
+                        int max_blocks, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const int g = grid_for(ntiles, max_blocks);
+    if (fp64)
+        hipLaunchKernelGGL(stage_kernel<double>, dim3(g), dim3(kBlock), 0, s, insts, tiles, ntiles, stage);
+    else
+        hipLaunchKernelGGL(stage_kernel<float>, dim3(g), dim3(kBlock), 0, s, insts, tiles, ntiles, stage);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_end(const Inst *insts, int ninst, hipStream_t s)
+{
+    hipLaunchKernelGGL(step_end_kernel, dim3((ninst + 63) / 64), dim3(64), 0, s, insts, ninst);
+    return hipGetLastError();
+}
+
+hipError_t launch_interval(bool fp64, const Inst *insts, const Tile *tiles, int ntiles, int max_blocks,
+                           hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const int g = grid_for(ntiles, max_blocks);
+    if (fp64)
+        hipLaunchKernelGGL(interval_kernel<double>, dim3(g), dim3(kBlock), 0, s, insts, tiles, ntiles);
+    else
+        hipLaunchKernelGGL(interval_kernel<float>, dim3(g), dim3(kBlock), 0, s, insts, tiles, ntiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_interval_end(const Inst *insts, int ninst, hipStream_t s)
+{
+    hipLaunchKernelGGL(interval_end_kernel, dim3((ninst + 63) / 64), dim3(64), 0, s, insts, ninst);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const Inst *insts, int inst, uint32_t npts, const double *l64, const double *k64,
+                       bool fp32, hipStream_t s)
+{
+    const int g = (int)((npts + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(init_kernel, dim3(g), dim3(kBlock), 0, s, insts, inst, l64, k64, fp32 ? 1 : 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(64), 0, s, insts, inst, fp32 ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_polish(const Inst *insts, int inst, uint32_t npts, int parity32, double shift_req,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(polish_switch_kernel, dim3(1), dim3(64), 0, s, insts, inst, shift_req);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int g = (int)((npts + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(polish_init_kernel, dim3(g), dim3(kBlock), 0, s, insts, inst, parity32);
+    return hipGetLastError();
+}
+
+hipError_t launch_output(const Inst *insts, int inst, uint32_t npts, bool from32, int parity, double *out,
+                         hipStream_t s)
+{
+    const int g = (int)((npts + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(output_kernel, dim3(g), dim3(kBlock), 0, s, insts, inst, from32 ? 1 : 0, parity, out);
+    return hipGetLastError();
+}
+
+}  // namespace hjr

@@ -1,0 +1,21 @@
+// hjr_kernels.hpp -- launch wrappers of the HJI VI kernels (host side).
+#pragma once
+
+#include "hjr_device.hpp"
+
+namespace hjr {
+
+hipError_t launch_stage(bool fp64, const Inst *insts, const Tile *tiles, int ntiles, int stage,
+                        int max_blocks, hipStream_t s);
+hipError_t launch_step_end(const Inst *insts, int ninst, hipStream_t s);
+hipError_t launch_interval(bool fp64, const Inst *insts, const Tile *tiles, int ntiles, int max_blocks,
+                           hipStream_t s);
+hipError_t launch_interval_end(const Inst *insts, int ninst, hipStream_t s);
+hipError_t launch_init(const Inst *insts, int inst, uint32_t npts, const double *l64, const double *k64,
+                       bool fp32, hipStream_t s);
+hipError_t launch_polish(const Inst *insts, int inst, uint32_t npts, int parity32, double shift_req,
+                         hipStream_t s);
+hipError_t launch_output(const Inst *insts, int inst, uint32_t npts, bool from32, int parity, double *out,
+                         hipStream_t s);
+
+}  // namespace hjr

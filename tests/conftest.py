@@ -19,3 +19,23 @@ def orc():
 
     oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def hjrlib():
+    """The HIP library, built in-tree if it is not there yet (hipcc cross-compiles on a CPU host)."""
+    from paper_1903_07715_amd import build, hjr
+
+    if not os.path.exists(hjr.LIB_PATH):
+        build.build()
+    hjr.load()
+    return hjr
+
+
+@pytest.fixture(scope="session")
+def gpu(hjrlib):
+    import torch
+
+    if not torch.cuda.is_available() or hjrlib.device_count() < 1:
+        pytest.fail("GPU test selected but no GPU is visible")
+    return torch.device("cuda:0")

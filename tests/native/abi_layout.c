@@ -1,0 +1,18 @@
+/* Prints sizeof/offsetof of the public structs as the C compiler lays them out. */
+#include <stddef.h>
+#include <stdio.h>
+
+#include "../../include/hjr.h"
+
+#define F(T, m) printf("%s.%s %zu\n", #T, #m, offsetof(T, m))
+int main(void)
+{
+    printf("hjr_grid %zu\nhjr_dynamics %zu\nhjr_options %zu\nhjr_result %zu\nhjr_problem %zu\nhjr_ctx_stats %zu\n",
+           sizeof(hjr_grid), sizeof(hjr_dynamics), sizeof(hjr_options), sizeof(hjr_result), sizeof(hjr_problem),
+           sizeof(hjr_ctx_stats));
+    F(hjr_grid, lo); F(hjr_grid, periodic_mask);
+    F(hjr_options, cfl); F(hjr_options, max_iter);
+    F(hjr_result, seconds); F(hjr_result, converged);
+    F(hjr_problem, opts); F(hjr_problem, l); F(hjr_problem, result); F(hjr_problem, status);
+    return 0;
+}

@@ -1,0 +1,144 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol include/hjr.h declares, and
+rejects bad arguments before touching a device.  No compute call runs here."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1903_07715_amd import hjr  # noqa: E402
+from paper_1903_07715_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hjr.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hjr_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(autouse=True)
+def _lib(hjrlib):
+    return hjrlib
+
+
+def test_library_exports_every_declared_symbol():
+    lib = hjr.load()
+    names = _declared()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(hjr.EXPORTED)
+    out = subprocess.run(["nm", "-D", "--defined-only", hjr.LIB_PATH], capture_output=True, text=True).stdout
+    for n in names:
+        assert re.search(rf"\bT {n}\b", out), n
+
+
+def test_struct_layouts_match_header():
+    """ctypes mirrors must match the C compiler's layout of include/hjr.h."""
+    exe = os.path.join(ROOT, "paper_1903_07715_amd", "_build", "abi_layout")
+    os.makedirs(os.path.dirname(exe), exist_ok=True)
+    subprocess.run(["gcc", "-std=c11", "-o", exe, os.path.join(ROOT, "tests", "native", "abi_layout.c")], check=True)
+    got = dict(ln.split() for ln in subprocess.run([exe], capture_output=True, text=True).stdout.splitlines())
+    mirrors = {"hjr_grid": hjr.Grid_, "hjr_dynamics": hjr.Dynamics_, "hjr_options": hjr.Options_,
+               "hjr_result": hjr.Result_, "hjr_problem": hjr.Problem_, "hjr_ctx_stats": hjr.CtxStats_}
+    for name, cls in mirrors.items():
+        assert int(got[name]) == C.sizeof(cls), name
+    for key, val in got.items():
+        if "." in key:
+            sname, field = key.split(".")
+            assert getattr(mirrors[sname], field).offset == int(val), key
+
+
+def test_defaults_and_strings():
+    assert hjr.abi_version() == 1
+    o = hjr.options()
+    assert (o.spatial, o.temporal, o.precision, o.cfl, o.tol) == (hjr.WENO5, hjr.TVDRK3, hjr.FP32_POLISH64, 0.5, 1e-6)
+    lib = hjr.load()
+    for s in (0, 1, 2, 3, -1, -2, -3, -4, -5, -6, -7):
+        assert lib.hjr_status_string(s).decode()
+
+
+def _call_solve(grid, dyn, **opts):
+    l = np.zeros(grid.size)
+    V = np.zeros(grid.size)
+    res = hjr.Result_()
+    o = hjr.options(**opts)
+    lib = hjr.load()
+    st = lib.hjr_solve(C.byref(hjr.grid_struct(grid)), C.byref(hjr.dyn_struct(dyn)),
+                       l.ctypes.data_as(C.POINTER(C.c_double)), None, C.byref(o),
+                       V.ctypes.data_as(C.POINTER(C.c_double)), C.byref(res))
+    return st, hjr.last_error()
+
+
+@pytest.mark.parametrize("case", [
+    ("ndim mismatch", W.Grid((11, 11, 11), (-1,) * 3, (1,) * 3), W.double_integrator(), {}),
+    ("too few nodes for WENO5", W.Grid((6, 11), (-1, -1), (1, 1)), W.double_integrator(), dict(spatial=hjr.WENO5)),
+    ("lo >= hi", W.Grid((11, 11), (1, -1), (1, 1)), W.double_integrator(), {}),
+    ("cfl > 1", W.Grid((11, 11), (-1, -1), (1, 1)), W.double_integrator(), dict(cfl=1.5)),
+    ("tol <= 0", W.Grid((11, 11), (-1, -1), (1, 1)), W.double_integrator(), dict(tol=0.0)),
+    ("bad precision", W.Grid((11, 11), (-1, -1), (1, 1)), W.double_integrator(), dict(precision=7)),
+    ("bad scheme", W.Grid((11, 11), (-1, -1), (1, 1)), W.double_integrator(), dict(spatial=3)),
+    ("interval without length", W.Grid((11, 11), (-1, -1), (1, 1)), W.double_integrator(),
+     dict(conv_mode=hjr.CONV_PER_INTERVAL, dt_report=0.0)),
+])
+def test_invalid_arguments_rejected_before_device_work(case):
+    name, g, d, opts = case
+    st, msg = _call_solve(g, d, **opts)
+    assert st == hjr.ERR_INVALID_ARG, (name, st, msg)
+    assert msg
+
+
+def test_unknown_dynamics_and_param_count():
+    g = W.Grid((11, 11), (-1, -1), (1, 1))
+    lib = hjr.load()
+    dyn = hjr.Dynamics_()
+    dyn.id = 9
+    dyn.n_params = 3
+    l = np.zeros(g.size)
+    V = np.zeros(g.size)
+    o = hjr.options()
+    st = lib.hjr_solve(C.byref(hjr.grid_struct(g)), C.byref(dyn), l.ctypes.data_as(C.POINTER(C.c_double)), None,
+                       C.byref(o), V.ctypes.data_as(C.POINTER(C.c_double)), None)
+    assert st == hjr.ERR_UNSUPPORTED
+    dyn.id = 1
+    dyn.n_params = 2
+    st = lib.hjr_solve(C.byref(hjr.grid_struct(g)), C.byref(dyn), l.ctypes.data_as(C.POINTER(C.c_double)), None,
+                       C.byref(o), V.ctypes.data_as(C.POINTER(C.c_double)), None)
+    assert st == hjr.ERR_INVALID_ARG
+
+
+def test_oversized_grid_rejected():
+    g = W.Grid((2000, 2000, 1000), (-1,) * 3, (1,) * 3)
+    st, _ = _call_solve(g, W.dubins3())
+    assert st == hjr.ERR_UNSUPPORTED
+
+
+def test_null_pointers_rejected():
+    lib = hjr.load()
+    assert lib.hjr_solve(None, None, None, None, None, None, None) == hjr.ERR_INVALID_ARG
+    assert lib.hjr_default_options(None) == hjr.ERR_INVALID_ARG
+    assert lib.hjr_poll(None, 1, None) == hjr.ERR_INVALID_ARG
+    assert lib.hjr_ctx_destroy(None) == hjr.OK
+
+
+def test_fast_division_is_exact():
+    exe = os.path.join(ROOT, "paper_1903_07715_amd", "_build", "fastdiv_check")
+    os.makedirs(os.path.dirname(exe), exist_ok=True)
+    subprocess.run(["g++", "-O2", "-std=c++17", "-o", exe, os.path.join(ROOT, "tests", "native", "fastdiv_check.cpp")],
+                   check=True)
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout
+
+
+def test_product_path_has_no_cpu_fallback():
+    """The binding never imports the oracle and has no compute code of its own."""
+    src = open(os.path.join(ROOT, "paper_1903_07715_amd", "hjr.py")).read()
+    assert "oracle" not in src.replace("no CPU fallback", "")
+    for f in os.listdir(os.path.join(ROOT, "paper_1903_07715_amd", "csrc")):
+        txt = open(os.path.join(ROOT, "paper_1903_07715_amd", "csrc", f)).read()
+        assert "hjr_oracle" not in txt and "or_solve" not in txt

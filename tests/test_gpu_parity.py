@@ -1,0 +1,213 @@
+"""GPU parity: the gfx950 kernels (through the C ABI) against the FP64 CPU oracle.
+
+Floating-point bars:
+  * one stage, FP64 kernels: |gpu - oracle| <= 1e-12 (1 + max|V|)  (rounding order only)
+  * one stage, FP32 kernels on FP32-rounded inputs: <= 2e-5 (1 + max|V|)
+  * converged FP64 solve: same iteration count, |gpu - oracle| <= 1e-9 max|l|
+  * converged FP32 + FP64-polish solve: |gpu - oracle| <= 1e-4 max|l| and no node where the two
+    disagree on the sign of V while |V_oracle| > 1e-4 max|l| (the unsafe set {V <= 0}).
+Integer outcomes (iteration counts, status codes, the max-change reduction of a stage given its
+output) are compared exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1903_07715_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SEED = W.SEED
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stage_cases():
+    di = W.Grid((37, 29), (-1.0, -1.2), (1.0, 0.9))
+    dub = W.Grid((19, 17, 23), (-5.0, -5.0, -math.pi), (5.0, 5.0, math.pi), (False, False, True))
+    uni = W.Grid((9, 11, 13, 8), (-5.0, -5.0, -math.pi, 0.0), (5.0, 5.0, math.pi, 2.0), (False, False, True, False))
+    quad = W.Grid((7, 7, 8, 7, 9, 7), (-6, -6, -6, -3, -3, -3), (6, 6, 6, 3, 3, 3))
+    return [
+        ("di", di, W.double_integrator(1.0, 0.8, 0.3)),
+        ("dubins", dub, W.dubins3(1.0, 1.5, 0.1, 0.05)),
+        ("unicycle", uni, W.unicycle4(1.0, 0.5, 0.1)),
+        ("unicycle-box", uni, W.unicycle4(1.0, 0.5, 0.1, box=True)),
+        ("quad", quad, W.quad6(1.2, (0.5, 0.3, 0.4))),
+    ]
+
+
+@pytest.mark.parametrize("case", _stage_cases(), ids=lambda c: c[0])
+def test_cfl_dt_matches_oracle(gpu, hjrlib, orc, case):
+    _, g, d = case
+    for cfl in (0.5, 0.8):
+        assert abs(hjrlib.cfl_dt(g, d, cfl) - orc.cfl_dt(g, d, cfl)) <= 1e-14 * orc.cfl_dt(g, d, cfl)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("scheme", [("upwind-euler", 1, 1), ("weno-rk3", 5, 3), ("upwind-rk3", 1, 3), ("weno-euler", 5, 1)],
+                         ids=lambda s: s[0])
+@pytest.mark.parametrize("game", [0, 1], ids=["avoid", "reach"])
+@pytest.mark.parametrize("case", _stage_cases(), ids=lambda c: c[0])
+def test_stage_parity(gpu, hjrlib, orc, case, scheme, precision, game):
+    torch = _torch()
+    name, g, d = case
+    _, spatial, temporal = scheme
+    rng = np.random.default_rng(SEED)
+    Vn = W.smooth_field(g, seed=SEED)
+    Vs = Vn + 0.05 * W.smooth_field(g, seed=SEED + 1, kinks=False)
+    l = Vn + rng.uniform(-0.05, 0.2, size=g.shape)  # the projection binds at some nodes
+    if precision == "fp32":
+        Vn, Vs, l = (a.astype(np.float32).astype(np.float64) for a in (Vn, Vs, l))
+    tdt = torch.float32 if precision == "fp32" else torch.float64
+    prec = hjrlib.FP32 if precision == "fp32" else hjrlib.FP64
+    dt = orc.cfl_dt(g, d, 0.5)
+    nodes = np.arange(g.size, dtype=np.int64)
+    scale = 1.0 + np.abs(Vn).max()
+    tol = 2e-5 * scale if precision == "fp32" else 1e-12 * scale
+    for stage in range(1, (3 if temporal == 3 else 1) + 1):
+        src = Vn if stage == 1 else Vs
+        t_src = torch.tensor(src, dtype=tdt, device=gpu)
+        t_vn = torch.tensor(Vn, dtype=tdt, device=gpu)
+        t_l = torch.tensor(l, dtype=tdt, device=gpu)
+        out = torch.empty_like(t_vn)
+        delta = hjrlib.stage_device(g, d, stage, dt, t_src, t_vn, t_l, out, game=game, spatial=spatial,
+                                    temporal=temporal, precision=prec)
+        torch.cuda.synchronize()
+        got = out.double().cpu().numpy()
+        ref = orc.stage_at(g, d, stage, dt, src, Vn, l, nodes, spatial=spatial, temporal=temporal,
+                           game=game).reshape(g.shape)
+        err = np.abs(got - ref).max()
+        assert err <= tol, (name, stage, err)
+        if delta is not None:
+            exact = np.abs(out.cpu().numpy().astype(np.float64) - t_vn.cpu().numpy().astype(np.float64)).max()
+            assert delta == exact
+
+
+def _sign_mismatch(Vg, Vo, band):
+    return int(np.sum(((Vg <= 0) != (Vo <= 0)) & (np.abs(Vo) > band)))
+
+
+def test_cfg1_double_integrator_fp64_cold_and_warm(gpu, hjrlib, orc):
+    """101^2 double integrator, box obstacle, upwind + Euler at CFL 0.8 in FP64, tol 1e-6; warm
+    start from the solution with |u| <= 0.8 (control grows: Remark 2)."""
+    p = W.di_box_problem(101, ubar=1.0)
+    p8 = W.di_box_problem(101, ubar=0.8)
+    opts = dict(spatial=1, temporal=1, cfl=0.8, tol=1e-6)
+    k, _ = orc.solve(p8.grid, p8.dyn, p8.l, **opts)
+    for warm in (None, k):
+        Vo, io = orc.solve(p.grid, p.dyn, p.l, warm, **opts)
+        Vg, rg, st = hjrlib.solve(p.grid, p.dyn, p.l, warm, precision=hjrlib.FP64, **opts)
+        assert st == hjrlib.OK and rg["converged"] == 1
+        assert rg["iterations"] == io["steps"]
+        assert abs(rg["t_final"] - io["t"]) < 1e-9
+        assert np.abs(Vg - Vo).max() <= 1e-9 * np.abs(p.l).max()
+
+
+@pytest.mark.parametrize("warm", [False, True], ids=["cold", "warm"])
+def test_dubins_fp32_polish_matches_oracle(gpu, hjrlib, orc, warm):
+    """Dubins car, WENO5 + TVD-RK3, FP32 with FP64 polish; warm start from the solution with the
+    disturbance bound halved (disturbance grows: exact by Theorem 2)."""
+    p = W.dubins_problem(41, dbar=0.1)
+    k = None
+    if warm:
+        q = W.dubins_problem(41, dbar=0.05)
+        k, _ = orc.solve(q.grid, q.dyn, q.l, **orc.problem_opts(q))
+    Vo, io = orc.solve(p.grid, p.dyn, p.l, k, **orc.problem_opts(p))
+    Vg, rg, st = hjrlib.solve(p.grid, p.dyn, p.l, k, precision=hjrlib.FP32_POLISH64, **hjrlib.problem_options(p))
+    band = 1e-4 * np.abs(p.l).max()
+    assert st == hjrlib.OK and rg["converged"] == 1 and rg["polish_iterations"] >= 1
+    assert np.abs(Vg - Vo).max() <= band
+    assert _sign_mismatch(Vg, Vo, band) == 0
+    Vg64, rg64, _ = hjrlib.solve(p.grid, p.dyn, p.l, k, precision=hjrlib.FP64, **hjrlib.problem_options(p))
+    assert rg64["iterations"] == io["steps"]
+    assert np.abs(Vg64 - Vo).max() <= 1e-9 * np.abs(p.l).max()
+
+
+def test_unicycle_fp32_polish_matches_oracle(gpu, hjrlib, orc):
+    p = W.unicycle_problem(13)
+    Vo, io = orc.solve(p.grid, p.dyn, p.l, max_iter=4000, **orc.problem_opts(p))
+    Vg, rg, st = hjrlib.solve(p.grid, p.dyn, p.l, None, precision=hjrlib.FP32_POLISH64, max_iter=4000,
+                              **hjrlib.problem_options(p))
+    band = 1e-4 * np.abs(p.l).max()
+    assert io["converged"] == 1 and st == hjrlib.OK
+    assert np.abs(Vg - Vo).max() <= band
+    assert _sign_mismatch(Vg, Vo, band) == 0
+
+
+def test_quad6_fixed_steps_match_oracle(gpu, hjrlib, orc):
+    """6-D quadrotor: ten FP64 steps, compared node by node."""
+    p = W.quad6_problem(9)
+    Vo, io = orc.solve(p.grid, p.dyn, p.l, max_iter=10, **orc.problem_opts(p))
+    Vg, rg, st = hjrlib.solve(p.grid, p.dyn, p.l, None, precision=hjrlib.FP64, max_iter=10,
+                              **hjrlib.problem_options(p))
+    assert st == hjrlib.NOT_CONVERGED and rg["iterations"] == 10 == io["steps"]
+    assert np.abs(Vg - Vo).max() <= 1e-10 * np.abs(p.l).max()
+
+
+def test_interval_mode_matches_oracle(gpu, hjrlib, orc):
+    """The paper's stopping rule: change across a 0.01 interval below 1e-3."""
+    p = W.di_box_problem(41, dbar=0.1)
+    opts = dict(spatial=1, temporal=1, cfl=0.8, tol=1e-3, conv_mode=1, dt_report=0.01)
+    Vo, io = orc.solve(p.grid, p.dyn, p.l, **opts)
+    Vg, rg, st = hjrlib.solve(p.grid, p.dyn, p.l, None, precision=hjrlib.FP64, **opts)
+    assert st == hjrlib.OK
+    assert rg["intervals"] == io["intervals"] and rg["iterations"] == io["steps"]
+    assert np.abs(Vg - Vo).max() <= 1e-10
+
+
+def test_reach_horizon_matches_oracle(gpu, hjrlib, orc):
+    g = W.Grid((51, 51), (-2, -2), (2, 2))
+    l = W.box_sdf(g, (0, 0), (0.1, 0.1))
+    d = W.double_integrator(1.0, 1.0, 0.0)
+    opts = dict(spatial=5, temporal=3, cfl=0.5, tol=1e-300, t_max=1.0, game=1)
+    Vo, io = orc.solve(g, d, l, **opts)
+    Vg, rg, st = hjrlib.solve(g, d, l, None, precision=hjrlib.FP64, **opts)
+    assert st == hjrlib.HORIZON and rg["converged"] == 2
+    assert rg["iterations"] == io["steps"] and abs(rg["t_final"] - 1.0) < 1e-9
+    assert np.abs(Vg - Vo).max() <= 1e-10
+
+
+def test_nonfinite_input_rejected(gpu, hjrlib):
+    p = W.di_box_problem(21)
+    l = p.l.copy()
+    l[3, 5] = np.inf
+    with pytest.raises(hjrlib.HJRError) as e:
+        hjrlib.solve(p.grid, p.dyn, l, None, **hjrlib.problem_options(p))
+    assert e.value.status == hjrlib.ERR_NONFINITE
+
+
+def test_max_iter_reports_not_converged(gpu, hjrlib):
+    p = W.dubins_problem(21)
+    V, r, st = hjrlib.solve(p.grid, p.dyn, p.l, None, max_iter=3, precision=hjrlib.FP32,
+                            **hjrlib.problem_options(p))
+    assert st == hjrlib.NOT_CONVERGED and r["iterations"] == 3 and r["converged"] == 0
+    assert np.all(np.isfinite(V))
+
+
+def test_repeat_runs_are_bitwise_identical(gpu, hjrlib):
+    p = W.dubins_problem(31)
+    a, ra, _ = hjrlib.solve(p.grid, p.dyn, p.l, None, **hjrlib.problem_options(p))
+    b, rb, _ = hjrlib.solve(p.grid, p.dyn, p.l, None, steps_per_sync=7, **hjrlib.problem_options(p))
+    assert np.array_equal(a, b)
+    assert (ra["iterations"], ra["polish_iterations"]) == (rb["iterations"], rb["polish_iterations"])
+
+
+def test_device_entry_point_matches_host_entry_point(gpu, hjrlib):
+    torch = _torch()
+    p = W.dubins_problem(25)
+    q = W.dubins_problem(25, dbar=0.05)
+    k, _, _ = hjrlib.solve(q.grid, q.dyn, q.l, None, **hjrlib.problem_options(q))
+    Vh, rh, _ = hjrlib.solve(p.grid, p.dyn, p.l, k, **hjrlib.problem_options(p))
+    l_t = torch.tensor(p.l, device=gpu)
+    k_t = torch.tensor(k, device=gpu)
+    V_t = torch.empty_like(l_t)
+    s = torch.cuda.Stream()
+    rd, st = hjrlib.solve_device(p.grid, p.dyn, l_t, k_t, V_t, stream=s, **hjrlib.problem_options(p))
+    torch.cuda.synchronize()
+    assert st == hjrlib.OK
+    assert np.array_equal(V_t.cpu().numpy(), Vh)
+    assert rd["iterations"] == rh["iterations"]
