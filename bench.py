@@ -37,6 +37,25 @@ BYTES_PER_NODE_STEP_RK3_FP32 = 36
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (packed FMA) peak
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of the FP32 stage kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# (scaled by a 1 GiB copy calibration), keyed by a hash of the kernel sources they were taken
+# from: a kernel changed since then reports null.
+MEASURED_TRAFFIC = {"c58372b302d98349": 9.811e6 + 3.953e6}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("hjr_device.hpp", "hjr_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_1903_07715_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -46,7 +65,23 @@ def parse():
     ap.add_argument("--n", type=int, default=101, help="grid side (default 101)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="instead of the benchmark, run 5 plain device copies of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """Plain device-to-device copies of a known size, to scale the HBM byte counters."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read_per_copy": n * 4, "bytes_written_per_copy": n * 4, "copies": 5}),
+          flush=True)
 
 
 def cpu_baseline(p, npts, seconds):
@@ -63,6 +98,7 @@ def cpu_baseline(p, npts, seconds):
     while True:
         V, _ = oracle.step(p.grid, p.dyn, V, p.l, dt, spatial=opts["spatial"], temporal=opts["temporal"])
         steps += 1
+        log(f"  oracle step {steps}: {time.perf_counter() - t0:.1f} s")
         if time.perf_counter() - t0 >= seconds:
             break
     el = time.perf_counter() - t0
@@ -78,6 +114,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import torch
 
     from paper_1903_07715_amd import hjr
@@ -91,21 +130,25 @@ def main():
     p = W.dubins_problem(n, dbar=0.1)
     q = W.dubins_problem(n, dbar=0.05)
     npts = p.grid.size
-    opts = hjr.problem_options(p, precision=hjr.FP32_POLISH64)
+    opts = hjr.problem_options(p, precision=hjr.FP32_POLISH64, max_iter=20000)
     stream = torch.cuda.Stream()
     l_t = torch.tensor(p.l, device=dev)
     lq_t = torch.tensor(q.l, device=dev)
     k_t = torch.empty_like(l_t)
     V_t = torch.empty_like(l_t)
     # warm-start function: the GPU solution of the smaller-disturbance problem
-    hjr.solve_device(q.grid, q.dyn, lq_t, None, k_t, stream=stream, **opts)
+    log(f"warm-start function: solving {q.name} (dbar 0.05)")
+    rq, _ = hjr.solve_device(q.grid, q.dyn, lq_t, None, k_t, stream=stream,
+                             **dict(opts, precision=hjr.FP64))
     torch.cuda.synchronize()
+    log(f"  done: {rq['iterations']}+{rq['polish_iterations']} steps in {rq['seconds']:.3f} s")
 
     def run(warm: bool):
         return hjr.solve_device(p.grid, p.dyn, l_t, k_t if warm else None, V_t, stream=stream, **opts)
 
-    for _ in range(args.warmup):
-        run(True)
+    for i in range(args.warmup):
+        r, _ = run(True)
+        log(f"warmup {i}: {r['iterations']}+{r['polish_iterations']} steps in {r['seconds']:.3f} s")
     torch.cuda.synchronize()
 
     hjr.profile_read(reset=True)
@@ -114,9 +157,10 @@ def main():
     t0 = time.perf_counter()
     updates = 0
     res = None
-    for _ in range(args.steps):
+    for i in range(args.steps):
         res, st = run(True)
         updates += (res["iterations"] + res["polish_iterations"]) * npts
+        log(f"timed warm solve {i}: {res['iterations']}+{res['polish_iterations']} steps")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     hjr.profile_enable(False)
@@ -126,8 +170,9 @@ def main():
     torch.cuda.synchronize()
     c0 = time.perf_counter()
     cres = None
-    for _ in range(args.steps):
+    for i in range(args.steps):
         cres, _ = run(False)
+        log(f"cold solve {i}: {cres['iterations']}+{cres['polish_iterations']} steps")
     torch.cuda.synchronize()
     cel = time.perf_counter() - c0
 
@@ -138,7 +183,8 @@ def main():
     flops = FLOP_PER_NODE_STAGE_DUBINS_WENO5 * npts
     achieved_tflops = flops / avg_s / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
+                "traffic": MEASURED_TRAFFIC.get(kernel_source_hash()),
                 "kernel": "stage_kernel<float> (WENO5 + LF + TVD-RK3 stage, Dubins 3-D)",
                 "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
                 "algorithmic_gbs": round(BYTES_PER_NODE_STEP_RK3_FP32 / 3 * npts / avg_s / 1e9, 1)}
@@ -164,6 +210,7 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(p, npts, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 

@@ -128,6 +128,11 @@ typedef struct {
     double t_max;           /* > 0: stop at this backward time (finite horizon); default 0 */
     double dt_max;          /* > 0: cap on dt; default 0 (a vanishing flow field uses dt = 1) */
     int64_t max_iter;       /* cap on time steps per phase; default 1000000 */
+    int64_t stall_window;   /* HJR_FP32 and HJR_FP32_POLISH64: after this many steps without the
+                               change dropping 1% below its smallest value in the phase, the phase
+                               ends as stalled.  A stalled FP32 phase hands over to the polish; a
+                               stalled final phase returns HJR_NOT_CONVERGED with converged = 3.
+                               0 = 128; < 0 disables.  HJR_FP64 solves never stop this way. */
 } hjr_options;
 
 typedef struct {
@@ -139,7 +144,8 @@ typedef struct {
     double dt;                  /* nominal CFL time step */
     double max_abs_l;           /* max |l| over the grid */
     double seconds;             /* wall-clock time of the device work */
-    int32_t converged;          /* 1 converged, 0 max_iter reached, 2 horizon reached */
+    int32_t converged;          /* 1 converged, 0 max_iter reached, 2 horizon reached,
+                                   3 stalled: the change stopped decreasing above tol */
     int32_t pad;
 } hjr_result;
 

@@ -423,6 +423,7 @@ static SolveState initial_state(const Request &r)
     st.cfl = r.opts.cfl;
     st.max_iter = r.opts.max_iter;
     st.conv_mode = r.opts.conv_mode;
+    st.stall_window = r.opts.stall_window == 0 ? 128 : (r.opts.stall_window < 0 ? 0 : r.opts.stall_window);
     st.last_delta = INFINITY;
     st.done = kRunning;  // set properly by setup_kernel
     return st;
@@ -666,7 +667,7 @@ public:
             res.last_delta = st.last_delta;
             res.dt = st.dt_nom;
             res.max_abs_l = st.max_abs_l;
-            res.converged = st.done == kConverged ? 1 : (st.done == kHorizon ? 2 : 0);
+            res.converged = st.done == kConverged ? 1 : (st.done == kHorizon ? 2 : (st.done == kStalled ? 3 : 0));
             r->status = st.done == kConverged ? HJR_OK : (st.done == kHorizon ? HJR_HORIZON : HJR_NOT_CONVERGED);
             const bool from32 = r->phase == 0 && r->fp32_first;
             const int parity = (r->opts.temporal == HJR_EULER) ? st.parity : 0;
@@ -878,6 +879,7 @@ hjr_status hjr_default_options(hjr_options *o)
     o->t_max = 0.0;
     o->dt_max = 0.0;
     o->max_iter = 1000000;
+    o->stall_window = 0;
     return HJR_OK;
 }
 

@@ -24,7 +24,7 @@ enum : int { kUpwind1 = 1, kWeno5 = 5 };
 enum : int { kEuler = 1, kRK3 = 3 };
 
 // state->done codes
-enum : int { kRunning = 0, kConverged = 1, kMaxIter = 2, kHorizon = 3, kNonFinite = 4 };
+enum : int { kRunning = 0, kConverged = 1, kMaxIter = 2, kHorizon = 3, kNonFinite = 4, kStalled = 5 };
 
 struct SolveState {
     double t;            // backward time marched (all phases)
@@ -44,6 +44,9 @@ struct SolveState {
     unsigned long long idelta_bits;  // max change across the current interval
     unsigned long long rate_bits;    // max_x sum alpha_i/dx_i (CFL reduction)
     unsigned long long lmax_bits;    // max |l|
+    double best_delta;    // smallest change seen in this phase (stall detection)
+    long long n_best;     // step at which best_delta last dropped by 1%
+    long long stall_window;  // > 0: stop the phase after this many steps without such a drop
     long long n;          // steps in the current phase
     long long max_iter;
     long long intervals;

@@ -175,6 +175,19 @@ __device__ __forceinline__ void apply_limits(SolveState *st)
     }
 }
 
+// FP32 phases: no new 1% low of the change for stall_window steps (or intervals) means the
+// iterate has reached the FP32 rounding floor.
+__device__ __forceinline__ void note_delta(SolveState *st, double delta, long long count)
+{
+    if (st->stall_window <= 0 || st->done != kRunning) return;
+    if (delta < 0.99 * st->best_delta) {
+        st->best_delta = delta;
+        st->n_best = count;
+    } else if (count - st->n_best >= st->stall_window) {
+        st->done = kStalled;
+    }
+}
+
 __global__ void step_end_kernel(const Inst *__restrict__ insts, int ninst)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -191,6 +204,7 @@ __global__ void step_end_kernel(const Inst *__restrict__ insts, int ninst)
     if (st->conv_mode == 0) {
         st->last_delta = delta;
         if (delta < st->tol) st->done = kConverged;
+        note_delta(st, delta, st->n);
         apply_limits(st);
     } else {
         st->t_int += dt;
@@ -238,6 +252,7 @@ __global__ void interval_end_kernel(const Inst *__restrict__ insts, int ninst)
     st->t_int = 0.0;
     st->last_delta = d;
     if (d < st->tol) st->done = kConverged;
+    note_delta(st, d, st->intervals);
     apply_limits(st);
 }
 
@@ -317,6 +332,9 @@ __global__ void setup_kernel(const Inst *__restrict__ insts, int inst, int fp32_
         }
     }
     st->tol = tol;
+    if (!fp32_phase) st->stall_window = 0;
+    st->best_delta = INFINITY;
+    st->n_best = 0;
     st->done = st->nonfinite ? kNonFinite : kRunning;
     st->dt_cur = next_dt(st);
     if (st->max_iter > 0 && st->n >= st->max_iter) st->done = kMaxIter;
@@ -341,6 +359,8 @@ __global__ void polish_switch_kernel(const Inst *__restrict__ insts, int inst, d
     st->check_interval = 0;
     st->t_int = 0.0;
     st->tol = st->tol_final;
+    st->best_delta = INFINITY;  // stall detection restarts for the polish
+    st->n_best = 0;
     st->dt_cur = next_dt(st);
 }
 

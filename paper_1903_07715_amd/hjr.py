@@ -46,7 +46,7 @@ class Options_(C.Structure):
                 ("precision", C.c_int32), ("conv_mode", C.c_int32), ("steps_per_sync", C.c_int32),
                 ("cfl", C.c_double), ("tol", C.c_double), ("tol_fp32", C.c_double),
                 ("polish_shift", C.c_double), ("dt_report", C.c_double), ("t_max", C.c_double),
-                ("dt_max", C.c_double), ("max_iter", C.c_int64)]
+                ("dt_max", C.c_double), ("max_iter", C.c_int64), ("stall_window", C.c_int64)]
 
 
 class Result_(C.Structure):
@@ -91,6 +91,13 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_1903_07715_amd.build`")
+        # One HIP runtime per process: PyTorch ships its own libamdhip64 with the same soname, so
+        # it is loaded first and libhjr binds to it (loading ours first would hand PyTorch a
+        # runtime it was not built against).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = C.CDLL(LIB_PATH)
         P = C.POINTER
         vp = C.c_void_p

@@ -127,15 +127,21 @@ def test_dubins_fp32_polish_matches_oracle(gpu, hjrlib, orc, warm):
     assert np.abs(Vg64 - Vo).max() <= 1e-9 * np.abs(p.l).max()
 
 
-def test_unicycle_fp32_polish_matches_oracle(gpu, hjrlib, orc):
+def test_unicycle_fixed_steps_match_oracle(gpu, hjrlib, orc):
+    """4-D unicycle: on this coarse grid WENO5 settles into a small limit cycle at the speed
+    edges instead of converging, so 150 steps are compared node by node in FP64 and FP32."""
     p = W.unicycle_problem(13)
-    Vo, io = orc.solve(p.grid, p.dyn, p.l, max_iter=4000, **orc.problem_opts(p))
-    Vg, rg, st = hjrlib.solve(p.grid, p.dyn, p.l, None, precision=hjrlib.FP32_POLISH64, max_iter=4000,
+    Vo, io = orc.solve(p.grid, p.dyn, p.l, max_iter=150, **orc.problem_opts(p))
+    L = np.abs(p.l).max()
+    Vg, rg, st = hjrlib.solve(p.grid, p.dyn, p.l, None, precision=hjrlib.FP64, max_iter=150,
                               **hjrlib.problem_options(p))
-    band = 1e-4 * np.abs(p.l).max()
-    assert io["converged"] == 1 and st == hjrlib.OK
-    assert np.abs(Vg - Vo).max() <= band
-    assert _sign_mismatch(Vg, Vo, band) == 0
+    assert st == hjrlib.NOT_CONVERGED and rg["iterations"] == 150 == io["steps"]
+    assert np.abs(Vg - Vo).max() <= 1e-10 * L
+    Vf, rf, st = hjrlib.solve(p.grid, p.dyn, p.l, None, precision=hjrlib.FP32, max_iter=150,
+                              **hjrlib.problem_options(p))
+    assert rf["iterations"] == 150
+    assert np.abs(Vf - Vo).max() <= 1e-4 * L
+    assert _sign_mismatch(Vf, Vo, 1e-4 * L) == 0
 
 
 def test_quad6_fixed_steps_match_oracle(gpu, hjrlib, orc):
