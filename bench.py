@@ -151,8 +151,7 @@ def main():
         log(f"warmup {i}: {r['iterations']}+{r['polish_iterations']} steps in {r['seconds']:.3f} s")
     torch.cuda.synchronize()
 
-    hjr.profile_read(reset=True)
-    hjr.profile_enable(True)
+    # timed region: warm solves
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     updates = 0
@@ -160,11 +159,24 @@ def main():
     for i in range(args.steps):
         res, st = run(True)
         updates += (res["iterations"] + res["polish_iterations"]) * npts
-        log(f"timed warm solve {i}: {res['iterations']}+{res['polish_iterations']} steps")
+        log(f"timed warm solve {i}: {res['iterations']}+{res['polish_iterations']} steps, status {st}")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+
+    # the same solves again with a HIP event pair around every stage-kernel launch, for the
+    # kernel's average launch duration (the events themselves slow the step loop a little, so
+    # they are kept out of the region `value` is measured on)
+    hjr.profile_read(reset=True)
+    hjr.profile_enable(True)
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for i in range(args.steps):
+        run(True)
+    torch.cuda.synchronize()
+    pel = time.perf_counter() - p0
     hjr.profile_enable(False)
     prof = hjr.profile_read(reset=True)
+    log(f"event-timed pass: {pel:.3f} s vs {el:.3f} s untimed")
 
     # cold solves on the same problem, for the warm/cold comparison (not part of `value`)
     torch.cuda.synchronize()
@@ -204,6 +216,7 @@ def main():
         "config": {"workload": f"dubins3d-{n}^3-weno5-tvdrk3-fp32-polish64-warm", "grid": [n, n, n],
                    "points": npts, "cfl": p.cfl, "tol": p.tol},
         "warm_solves_per_s": args.steps / el,
+        "event_pass_seconds": pel,
         "cold_solves_per_s": args.steps / cel,
         "warm_iterations": [res["iterations"], res["polish_iterations"]],
         "cold_iterations": [cres["iterations"], cres["polish_iterations"]],

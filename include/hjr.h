@@ -78,7 +78,7 @@ enum {
 };
 
 /* Grid.  ndim in 1..6 and equal to the model's state dimension; n[i] >= 3 (>= 7 with WENO5);
- * lo[i] < hi[i]; the product of n must stay below 2^31. */
+ * lo[i] < hi[i]; the product of n must stay below 2^29 (an FP64 field stays below 4 GiB). */
 typedef struct {
     int32_t ndim;
     int32_t n[HJR_MAX_DIM];
@@ -127,10 +127,11 @@ typedef struct {
     double dt_report;       /* interval length of HJR_CONV_PER_INTERVAL; default 0.01 */
     double t_max;           /* > 0: stop at this backward time (finite horizon); default 0 */
     double dt_max;          /* > 0: cap on dt; default 0 (a vanishing flow field uses dt = 1) */
-    int64_t max_iter;       /* cap on time steps per phase; default 1000000 */
+    int64_t max_iter;       /* cap on time steps per phase; default 100000 */
     int64_t stall_window;   /* HJR_FP32 and HJR_FP32_POLISH64: after this many steps without the
-                               change dropping 1% below its smallest value in the phase, the phase
-                               ends as stalled.  A stalled FP32 phase hands over to the polish; a
+                               change dropping 1% below its smallest value in the phase (16 times
+                               as many while the change is above 64 tol), the phase ends as
+                               stalled.  A stalled FP32 phase hands over to the polish; a
                                stalled final phase returns HJR_NOT_CONVERGED with converged = 3.
                                0 = 128; < 0 disables.  HJR_FP64 solves never stop this way. */
 } hjr_options;
@@ -185,7 +186,9 @@ typedef struct {
 hjr_status hjr_batch_solve(int32_t count, hjr_problem *problems);
 
 /* Kernel-level entry points (device arrays, element type FP32 when precision == HJR_FP32, else
- * FP64).  They run exactly the kernels the solvers run.
+ * FP64).  They run exactly the kernels the solvers run (the stage kernel specialised to the
+ * model and scheme, with the nodes-per-thread the autotuner chose for this size class in this
+ * process, else 4).
  *   hjr_cfl_dt: dt = cfl / max_x sum_i alpha_i(x)/dx_i (1 when that maximum is 0), capped by
  *     dt_max > 0; computed by a device reduction.
  *   hjr_stage_device: one time-integrator stage at every node.  Vs is the field the stencil is

@@ -34,8 +34,8 @@ def flags() -> list:
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def _compile(src: str, obj: str) -> None:
-    cmd = [hipcc()] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, obj: str, extra=()) -> None:
+    cmd = [hipcc()] + flags() + list(extra) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     # the host pass does not know the GPU target feature; that warning is expected
     err = "\n".join(ln for ln in r.stderr.splitlines() if "packed-fp32-ops" not in ln)
@@ -45,22 +45,23 @@ def _compile(src: str, obj: str) -> None:
         sys.stderr.write(err + "\n")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source and link libhjr.so.  Always recompiles."""
-    objdir = os.path.join(HERE, "_build")
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile every HIP source and link libhjr.so (or `out`).  Always recompiles."""
+    objdir = os.path.join(HERE, "_build", os.path.basename(out))
     os.makedirs(objdir, exist_ok=True)
     objs = [os.path.join(objdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    extra = [f"-D{d}" for d in defines]
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        list(ex.map(_compile, SOURCES, objs))
-    tmp = LIB + f".tmp{os.getpid()}"
+        list(ex.map(lambda so: _compile(so[0], so[1], extra), zip(SOURCES, objs)))
+    tmp = out + f".tmp{os.getpid()}"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link of libhjr.so failed:\n" + r.stderr)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -18,6 +18,7 @@
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -135,7 +136,7 @@ static hjr_status validate(const hjr_grid *g, const hjr_dynamics *dy, int spatia
         if (!std::isfinite(g->lo[d]) || !std::isfinite(g->hi[d]) || !(g->hi[d] > g->lo[d]))
             return fail(HJR_ERR_INVALID_ARG, "dim %d: need lo < hi", d);
         N *= (uint64_t)g->n[d];
-        if (N >= (1ull << 31)) return fail(HJR_ERR_UNSUPPORTED, "grid has 2^31 or more nodes");
+        if (N >= (1ull << 29)) return fail(HJR_ERR_UNSUPPORTED, "grid has 2^29 or more nodes");
     }
     if (g->periodic_mask >> g->ndim) return fail(HJR_ERR_INVALID_ARG, "periodic_mask names a missing dim");
     *npts_out = N;
@@ -430,6 +431,73 @@ static SolveState initial_state(const Request &r)
 }
 
 // --------------------------------------------------------------------------------------------
+// Autotuner: nodes per thread of the stage kernels, per (precision, model, scheme, size class).
+// A choice is found by timing trial launches on the instances at hand and is kept for the rest
+// of the process; with HJR_TUNE_CACHE=<file> choices are also read from and appended to a
+// small JSON file, so later processes skip the trials.
+// --------------------------------------------------------------------------------------------
+
+class Tuner {
+public:
+    static Tuner &get()
+    {
+        static Tuner *t = new Tuner();
+        return *t;
+    }
+    static std::string key(int prec, int dyn, int spatial, uint64_t nodes)
+    {
+        int b = 0;
+        while ((2ull << b) <= nodes) ++b;
+        char buf[64];
+        snprintf(buf, sizeof buf, "fp%d_dyn%d_sp%d_n2^%d", prec ? 64 : 32, dyn, spatial, b);
+        return buf;
+    }
+    int lookup(const std::string &k)
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        load_file();
+        auto it = map_.find(k);
+        return it == map_.end() ? 0 : it->second;
+    }
+    void store(const std::string &k, int npt)
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        map_[k] = npt;
+        const char *path = getenv("HJR_TUNE_CACHE");
+        if (!path || !*path) return;
+        FILE *f = fopen(path, "w");
+        if (!f) return;
+        fprintf(f, "{\n");
+        size_t i = 0;
+        for (auto &kv : map_) fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < map_.size() ? "," : "");
+        fprintf(f, "}\n");
+        fclose(f);
+    }
+
+private:
+    void load_file()
+    {
+        if (loaded_) return;
+        loaded_ = true;
+        const char *path = getenv("HJR_TUNE_CACHE");
+        if (!path || !*path) return;
+        FILE *f = fopen(path, "r");
+        if (!f) return;
+        char line[256];
+        while (fgets(line, sizeof line, f)) {
+            char k[128];
+            int v = 0;
+            if (sscanf(line, " \"%127[^\"]\" : %d", k, &v) == 2 && (v == 1 || v == 2 || v == 4 || v == 8))
+                map_[k] = v;
+        }
+        fclose(f);
+    }
+    std::mutex mu_;
+    std::map<std::string, int> map_;
+    bool loaded_ = false;
+};
+
+// --------------------------------------------------------------------------------------------
 // Engine
 // --------------------------------------------------------------------------------------------
 
@@ -464,6 +532,12 @@ public:
         slots_.assign(cap_, nullptr);
         hist_.assign(cap_, Hist{});
         HJR_HIP(hipDeviceGetAttribute(&cus_, hipDeviceAttributeMultiprocessorCount, device_));
+        if (const char *mb = getenv("HJR_MAX_BLOCKS")) max_blocks_ = atoi(mb);
+        if (const char *fu = getenv("HJR_FUSED")) fused_ = atoi(fu) != 0;
+        if (const char *np = getenv("HJR_NPT")) npt_override_ = atoi(np);
+        if (npt_override_ != 1 && npt_override_ != 2 && npt_override_ != 4 && npt_override_ != 8) npt_override_ = 0;
+        if (const char *at = getenv("HJR_AUTOTUNE")) autotune_ = atoi(at) != 0;
+        if (const char *gr = getenv("HJR_GRAPHS")) graphs_ = atoi(gr) != 0;
         return HJR_OK;
     }
 
@@ -475,6 +549,7 @@ public:
             (void)hipEventDestroy(e.b);
         }
         evs_.clear();
+        drop_graphs();
         for (Request *r : slots_)
             if (r) drop(r);
         Pool::get().release(d_states_);
@@ -495,6 +570,13 @@ public:
     }
 
     hipStream_t stream() const { return stream_; }
+    // Replay captured HIP graphs of whole chunks (worth it for engines that live across many
+    // chunks of the same length; HJR_GRAPHS=0/1 overrides).
+    void prefer_graphs(bool on)
+    {
+        const char *gr = getenv("HJR_GRAPHS");
+        graphs_ = gr ? atoi(gr) != 0 : on;
+    }
     int active() const { return nactive_; }
     bool has_free_slot() const { return nactive_ < cap_; }
     int64_t launches() const { return launches_; }
@@ -548,31 +630,15 @@ public:
         return HJR_OK;
     }
 
-    // Issue m steps for every running instance, then read the states back.
-    hjr_status run_chunk(int m)
+    // Enqueue m steps for every running instance.
+    hjr_status enqueue_steps(int m, bool prof)
     {
-        if (dirty_) {
-            hjr_status s = rebuild();
-            if (s != HJR_OK) return s;
-        }
         const int ninst = top_slot_ + 1;
-        const bool prof = g_profile_on.load() != 0;
-        nev_ = 0;
         for (int step = 0; step < m; ++step) {
             for (int stage = 0; stage < max_stages_; ++stage) {
                 for (int prec = 0; prec < 2; ++prec) {
-                    const int nt = prec ? n64_ : n32_;
-                    if (nt <= 0) continue;
-                    hipEvent_t a = nullptr, b = nullptr;
-                    if (prof) {
-                        hjr_status s = event_pair(&a, &b, prec, stage, (int64_t)nt * kBlock);
-                        if (s != HJR_OK) return s;
-                        HJR_HIP(hipEventRecord(a, stream_));
-                    }
-                    HJR_HIP(launch_stage(prec != 0, d_insts_, prec ? d_tiles64_ : d_tiles32_, nt, stage, max_blocks_,
-                                         stream_));
-                    if (prof) HJR_HIP(hipEventRecord(b, stream_));
-                    ++launches_;
+                    hjr_status s = launch_stage_all(prec, stage, prof);
+                    if (s != HJR_OK) return s;
                 }
             }
             HJR_HIP(launch_step_end(d_insts_, ninst, stream_));
@@ -583,6 +649,56 @@ public:
                 HJR_HIP(launch_interval_end(d_insts_, ninst, stream_));
                 launches_ += 3;
             }
+        }
+        return HJR_OK;
+    }
+
+    // Issue m steps (replaying a captured HIP graph of them when graphs are on), then read the
+    // states back.
+    hjr_status run_chunk(int m)
+    {
+        if (dirty_) {
+            hjr_status s = rebuild();
+            if (s != HJR_OK) return s;
+        }
+        const int ninst = top_slot_ + 1;
+        const bool prof = g_profile_on.load() != 0;
+        nev_ = 0;
+        bool done = false;
+        if (graphs_ && !prof) {
+            hipGraphExec_t exec = nullptr;
+            auto it = graphs_by_m_.find(m);
+            if (it != graphs_by_m_.end()) {
+                exec = it->second;
+            } else {
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    const int64_t l0 = launches_;
+                    hjr_status s = enqueue_steps(m, false);
+                    launches_ = l0;
+                    e = hipStreamEndCapture(stream_, &g);
+                    if (s != HJR_OK && e == hipSuccess) e = hipErrorUnknown;
+                }
+                if (e == hipSuccess) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+                if (g) (void)hipGraphDestroy(g);
+                if (e != hipSuccess) {
+                    (void)hipGetLastError();
+                    graphs_ = false;  // fall back to direct launches for this engine
+                    exec = nullptr;
+                } else {
+                    graphs_by_m_[m] = exec;
+                }
+            }
+            if (exec) {
+                HJR_HIP(hipGraphLaunch(exec, stream_));
+                launches_ += (int64_t)m * (max_stages_ * ((int)segs_[0].size() + (int)segs_[1].size()) + 1);
+                done = true;
+            }
+        }
+        if (!done) {
+            hjr_status s = enqueue_steps(m, prof);
+            if (s != HJR_OK) return s;
         }
         ++chunks_;
         HJR_HIP(hipMemcpyAsync(h_states_, d_states_, sizeof(SolveState) * ninst, hipMemcpyDeviceToHost, stream_));
@@ -600,6 +716,12 @@ public:
             }
         }
         return HJR_OK;
+    }
+
+    void drop_graphs()
+    {
+        for (auto &kv : graphs_by_m_) (void)hipGraphExecDestroy(kv.second);
+        graphs_by_m_.clear();
     }
 
     // Steps until the first running instance is expected to meet its threshold, from the decay
@@ -731,7 +853,12 @@ private:
 
     hjr_status rebuild()
     {
-        std::vector<Tile> t32, t64;
+        // tiles grouped by (precision, model, scheme); each group is a contiguous segment
+        struct G {
+            std::vector<int> slots;
+            uint64_t nodes = 0;
+        };
+        std::map<int, G> groups[2];
         top_slot_ = -1;
         max_stages_ = 1;
         any_interval_ = false;
@@ -741,14 +868,59 @@ private:
             top_slot_ = i;
             if (r->opts.temporal == HJR_TVDRK3) max_stages_ = 3;
             if (r->opts.conv_mode == HJR_CONV_PER_INTERVAL) any_interval_ = true;
-            const bool fp64 = !(r->phase == 0 && r->fp32_first);
-            auto &dst = fp64 ? t64 : t32;
-            for (uint64_t s = 0; s < r->npts; s += kBlock) dst.push_back(Tile{i, (uint32_t)s});
+            const int fp64 = !(r->phase == 0 && r->fp32_first) ? 1 : 0;
+            G &g = groups[fp64][r->dyn.id * 8 + r->opts.spatial];
+            g.slots.push_back(i);
+            g.nodes += r->npts;
         }
         if (top_slot_ < 0) top_slot_ = 0;
-        n32_ = (int)t32.size();
-        n64_ = (int)t64.size();
-        const size_t need = (t32.size() + t64.size() + 2) * sizeof(Tile);
+        std::vector<Tile> t[2];
+        for (int p = 0; p < 2; ++p) {
+            segs_[p].clear();
+            for (auto &kv : groups[p]) {
+                const int dyn = kv.first / 8, sp = kv.first % 8;
+                int npt = kFusedNpt;
+                if (!fused_) {
+                    npt = npt_override_;
+                    if (!npt) {
+                        const std::string k = Tuner::key(p, dyn, sp, kv.second.nodes);
+                        npt = Tuner::get().lookup(k);
+                        if (!npt && autotune_) {
+                            hjr_status s = tune(p, dyn, sp, kv.second.slots, &npt);
+                            if (s != HJR_OK) return s;
+                            Tuner::get().store(k, npt);
+                        }
+                        if (!npt) npt = kFusedNpt;
+                    }
+                }
+                const int off = (int)t[p].size();
+                append_tiles(kv.second.slots, npt, t[p]);
+                segs_[p].push_back(Seg{dyn, sp, npt, off, (int)t[p].size() - off});
+            }
+        }
+        n32_ = (int)t[0].size();
+        n64_ = (int)t[1].size();
+        for (int p = 0; p < 2; ++p) {
+            nodes_[p] = 0;
+            for (auto &kv : groups[p]) nodes_[p] += (int64_t)kv.second.nodes;
+        }
+        hjr_status s = upload_tiles(t[0], t[1]);
+        if (s != HJR_OK) return s;
+        drop_graphs();
+        dirty_ = false;
+        return HJR_OK;
+    }
+
+    void append_tiles(const std::vector<int> &slots, int npt, std::vector<Tile> &out)
+    {
+        const uint64_t step = (uint64_t)npt * kBlock;
+        for (int i : slots)
+            for (uint64_t s = 0; s < slots_[i]->npts; s += step) out.push_back(Tile{i, (uint32_t)s, npt});
+    }
+
+    hjr_status upload_tiles(const std::vector<Tile> &a, const std::vector<Tile> &b)
+    {
+        const size_t need = (a.size() + b.size() + 2) * sizeof(Tile);
         if (need > tiles_cap_) {
             HJR_HIP(hipStreamSynchronize(stream_));
             Pool::get().release(d_tiles32_);
@@ -761,15 +933,105 @@ private:
         }
         // staging is reused: earlier copies from it must have completed
         HJR_HIP(hipStreamSynchronize(stream_));
-        std::memcpy(h_tiles_, t32.data(), t32.size() * sizeof(Tile));
-        std::memcpy((char *)h_tiles_ + tiles_cap_, t64.data(), t64.size() * sizeof(Tile));
-        if (n32_) HJR_HIP(hipMemcpyAsync(d_tiles32_, h_tiles_, n32_ * sizeof(Tile), hipMemcpyHostToDevice, stream_));
-        if (n64_)
-            HJR_HIP(hipMemcpyAsync(d_tiles64_, (char *)h_tiles_ + tiles_cap_, n64_ * sizeof(Tile),
+        std::memcpy(h_tiles_, a.data(), a.size() * sizeof(Tile));
+        std::memcpy((char *)h_tiles_ + tiles_cap_, b.data(), b.size() * sizeof(Tile));
+        if (!a.empty())
+            HJR_HIP(hipMemcpyAsync(d_tiles32_, h_tiles_, a.size() * sizeof(Tile), hipMemcpyHostToDevice, stream_));
+        if (!b.empty())
+            HJR_HIP(hipMemcpyAsync(d_tiles64_, (char *)h_tiles_ + tiles_cap_, b.size() * sizeof(Tile),
                                    hipMemcpyHostToDevice, stream_));
-        dirty_ = false;
         return HJR_OK;
     }
+
+    // Time trial launches of one group for each nodes-per-thread candidate.  The trials write
+    // only buffers the next real step recomputes, and any max-change they accumulate (Euler) is
+    // cleared afterwards.
+    hjr_status tune(int prec, int dyn, int spatial, const std::vector<int> &slots, int *best_npt)
+    {
+        static const int cands[] = {4, 2, 8, 1};  // ties (within 2%) go to the earlier entry
+        float best = 1e30f;
+        *best_npt = kFusedNpt;
+        hipEvent_t a, b;
+        HJR_HIP(hipEventCreate(&a));
+        HJR_HIP(hipEventCreate(&b));
+        for (int npt : cands) {
+            std::vector<Tile> t, none;
+            append_tiles(slots, npt, t);
+            hjr_status s = prec ? upload_tiles(none, t) : upload_tiles(t, none);
+            if (s != HJR_OK) return s;
+            const Tile *dt = prec ? d_tiles64_ : d_tiles32_;
+            const int nt = (int)t.size();
+            // a trial is RK stages 1 and 2, which write only the stage buffers A and B (stage 3
+            // would overwrite the iterate); Euler instances run their single stage into the
+            // ping-pong buffer and skip the second launch
+            auto trial = [&]() -> hipError_t {
+                hipError_t e = launch_stage_one(prec != 0, dyn, spatial, npt, d_insts_, dt, nt, 0, max_blocks_, stream_);
+                if (e == hipSuccess)
+                    e = launch_stage_one(prec != 0, dyn, spatial, npt, d_insts_, dt, nt, 1, max_blocks_, stream_);
+                return e;
+            };
+            HJR_HIP(trial());
+            // best of five: the least disturbed measurement
+            float mine = 1e30f;
+            for (int r = 0; r < 5; ++r) {
+                HJR_HIP(hipEventRecord(a, stream_));
+                HJR_HIP(trial());
+                HJR_HIP(hipEventRecord(b, stream_));
+                HJR_HIP(hipEventSynchronize(b));
+                float ms = 0.f;
+                HJR_HIP(hipEventElapsedTime(&ms, a, b));
+                mine = std::min(mine, ms);
+            }
+            if (mine < 0.98f * best) {
+                best = mine;
+                *best_npt = npt;
+            }
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        HJR_HIP(launch_clear_deltas(d_insts_, top_slot_ + 1, stream_));
+        ++tunings_;
+        return HJR_OK;
+    }
+
+    // One stage over every tile of one precision: a single fused launch, or one launch per
+    // (model, scheme) group with the kernel specialised to it.
+    hjr_status launch_stage_all(int prec, int stage, bool prof)
+    {
+        const int nt = prec ? n64_ : n32_;
+        if (nt <= 0) return HJR_OK;
+        const Tile *tl = prec ? d_tiles64_ : d_tiles32_;
+        hipEvent_t a = nullptr, b = nullptr;
+        if (prof) {
+            hjr_status s = event_pair(&a, &b, prec, stage, nodes_[prec]);
+            if (s != HJR_OK) return s;
+            HJR_HIP(hipEventRecord(a, stream_));
+        }
+        if (fused_) {
+            HJR_HIP(launch_stage(prec != 0, d_insts_, tl, nt, stage, max_blocks_, stream_));
+            ++launches_;
+        } else {
+            for (const Seg &g : segs_[prec]) {
+                HJR_HIP(launch_stage_one(prec != 0, g.dyn, g.spatial, g.npt, d_insts_, tl + g.off, g.count, stage,
+                                         max_blocks_, stream_));
+                ++launches_;
+            }
+        }
+        if (prof) HJR_HIP(hipEventRecord(b, stream_));
+        return HJR_OK;
+    }
+
+    struct Seg {
+        int dyn, spatial, npt, off, count;
+    };
+    std::vector<Seg> segs_[2];
+    std::map<int, hipGraphExec_t> graphs_by_m_;
+    bool graphs_ = false;
+    int64_t nodes_[2] = {0, 0};
+    bool fused_ = false;
+    bool autotune_ = true;
+    int npt_override_ = 0;
+    int tunings_ = 0;
 
     int cap_;
     int device_ = 0;
@@ -878,7 +1140,7 @@ hjr_status hjr_default_options(hjr_options *o)
     o->dt_report = 0.01;
     o->t_max = 0.0;
     o->dt_max = 0.0;
-    o->max_iter = 1000000;
+    o->max_iter = 100000;
     o->stall_window = 0;
     return HJR_OK;
 }
@@ -980,6 +1242,7 @@ hjr_status hjr_batch_solve(int32_t count, hjr_problem *problems)
     Engine E(count);
     hjr_status s = E.init(nullptr);
     if (s != HJR_OK) return s;
+    E.prefer_graphs(true);
     s = run_all(E, reqs, true, lh, kh, sps);
     hjr_status first = HJR_OK;
     for (int i = 0; i < count; ++i) {
@@ -1114,8 +1377,17 @@ hjr_status hjr_stage_device(const hjr_grid *grid, const hjr_dynamics *dyn, int32
     hs.dt_cur = dt;
     hs.dt_nom = dt;
     hs.done = kRunning;
+    // the kernel variant the solvers use: the specialised kernel with the nodes-per-thread the
+    // tuner chose for this size class (HJR_NPT overrides; HJR_FUSED=1 selects the fused kernel)
+    bool fused = false;
+    if (const char *fu = getenv("HJR_FUSED")) fused = atoi(fu) != 0;
+    int npt = 0;
+    if (const char *np = getenv("HJR_NPT")) npt = atoi(np);
+    if (npt != 1 && npt != 2 && npt != 4 && npt != 8) npt = 0;
+    if (!npt) npt = Tuner::get().lookup(Tuner::key(f32 ? 0 : 1, dyn->id, spatial, r.npts));
+    if (!npt || fused) npt = kFusedNpt;
     std::vector<Tile> tiles;
-    for (uint64_t s0 = 0; s0 < r.npts; s0 += kBlock) tiles.push_back(Tile{0, (uint32_t)s0});
+    for (uint64_t s0 = 0; s0 < r.npts; s0 += (uint64_t)npt * kBlock) tiles.push_back(Tile{0, (uint32_t)s0, npt});
     void *dtl = nullptr;
     if (e == hipSuccess) e = Pool::get().alloc(&dtl, tiles.size() * sizeof(Tile));
     if (e == hipSuccess) e = hipMemcpyAsync((void *)I.tab64, t64.data(), t64.size() * 8, hipMemcpyHostToDevice, st);
@@ -1123,7 +1395,12 @@ hjr_status hjr_stage_device(const hjr_grid *grid, const hjr_dynamics *dyn, int32
     if (e == hipSuccess) e = hipMemcpyAsync(dstate, &hs, sizeof hs, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(dinst, &I, sizeof I, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(dtl, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = launch_stage(!f32, dinst, (const Tile *)dtl, (int)tiles.size(), k, 0, st);
+    if (e == hipSuccess) {
+        if (fused)
+            e = launch_stage(!f32, dinst, (const Tile *)dtl, (int)tiles.size(), k, 0, st);
+        else
+            e = launch_stage_one(!f32, dyn->id, spatial, npt, dinst, (const Tile *)dtl, (int)tiles.size(), k, 0, st);
+    }
     SolveState after;
     if (e == hipSuccess) e = hipMemcpyAsync(&after, dstate, sizeof after, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -1236,6 +1513,7 @@ hjr_status hjr_ctx_create(int32_t device, size_t hbm_budget_bytes, hjr_ctx **out
     c->engine = std::make_unique<Engine>(256);
     hjr_status s = c->engine->init(nullptr);
     if (s != HJR_OK) return s;
+    c->engine->prefer_graphs(true);
     hjr_ctx *p = c.release();
     p->worker = std::thread([p] { p->loop(); });
     *out = p;

@@ -17,7 +17,8 @@
 namespace hjr {
 
 constexpr int kMaxDim = 6;
-constexpr int kBlock = 256;        // threads per workgroup = nodes per tile
+constexpr int kBlock = 256;        // threads per workgroup
+constexpr int kFusedNpt = 4;       // nodes per thread of the fused (all-model) stage kernel
 
 enum : int { kDynDI = 1, kDynDubins = 2, kDynUnicycle = 3, kDynQuad = 4 };
 enum : int { kUpwind1 = 1, kWeno5 = 5 };
@@ -106,9 +107,12 @@ struct Inst {
     SolveState *state;
 };
 
+// A tile is npt * kBlock consecutive nodes of one instance's flattened grid (npt nodes per
+// thread, kBlock apart).
 struct Tile {
     int inst;
     uint32_t start;
+    int npt;
 };
 
 template <typename T> struct Fields;
@@ -136,53 +140,105 @@ template <> struct Fields<double> {
 __device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double recip(double x) { return 1.0 / x; }
 
+// 2^-floor(log2 x) for a positive normal x, from the exponent bits (no division).
+__device__ inline float pow2_recip(float x)
+{
+    return __uint_as_float(0x7f000000u - (__float_as_uint(x) & 0x7f800000u));
+}
+__device__ inline double pow2_recip(double x)
+{
+    return __longlong_as_double((long long)(0x7fe0000000000000ull -
+                                            ((unsigned long long)__double_as_longlong(x) & 0x7ff0000000000000ull)));
+}
+
+// Loads and stores through the global address space (the field pointers come from device
+// memory, so without the cast the compiler would use generic "flat" accesses).  The element
+// offset is turned into a 32-bit byte offset (every array is below 4 GiB), so the access is a
+// uniform 64-bit base plus one 32-bit per-lane offset.
+template <typename T>
+__device__ __forceinline__ T ldg(const T *p, uint32_t i)
+{
+    const uint32_t b = i * (uint32_t)sizeof(T);
+    return *(const __attribute__((address_space(1))) T *)((const __attribute__((address_space(1))) char *)p + b);
+}
+template <typename T>
+__device__ __forceinline__ void stg(T *p, uint32_t i, T v)
+{
+    const uint32_t b = i * (uint32_t)sizeof(T);
+    *(__attribute__((address_space(1))) T *)((__attribute__((address_space(1))) char *)p + b) = v;
+}
+
 // ---------------------------------------------------------------------------------------------
-// WENO5 one-sided derivative from five first differences (Jiang-Peng smoothness indicators,
-// ideal weights 0.1/0.6/0.3, eps = 1e-6 max v^2 + 1e-18).  The weights a_k = g_k / (S_k + eps)^2
-// are normalised without forming them: with t_k = S_k/eps + 1 in [1, 3.4e7], the ratio
-// a_k / sum a equals b_k / sum b for b_k = g_k prod_{j != k} t_j^2, which stays inside the FP32
-// range and needs a single reciprocal per derivative.
+// WENO5 one-sided derivatives at a node from its six first differences d[k] (offset k-2):
+// D- from (d0..d4), D+ from the mirrored (d5..d1) (Jiang-Peng smoothness indicators, ideal
+// weights 0.1/0.6/0.3, eps = 1e-6 max v^2 + 1e-18).  The two share the second differences
+// centred at offsets 0 and 1 and four of the five squares in eps.  The weights
+// a_k = g_k / (S_k + eps)^2 are normalised without forming them: with t_k = (S_k + eps) * 2^-e,
+// e the exponent of eps, t_k lies in [1, 7e7] and a_k / sum a = b_k / sum b for
+// b_k = g_k prod_{j != k} t_j^2, which stays inside the FP32 range and needs one reciprocal.
 // ---------------------------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ T weno5(T v1, T v2, T v3, T v4, T v5)
+__device__ __forceinline__ T weno5_combine(T S1, T S2, T S3, T eps, T phi1, T phi2, T phi3)
 {
-    const T c13_12 = T(13.0 / 12.0);
-    T phi1 = v1 * T(1.0 / 3.0) - v2 * T(7.0 / 6.0) + v3 * T(11.0 / 6.0);
-    T phi2 = -v2 * T(1.0 / 6.0) + v3 * T(5.0 / 6.0) + v4 * T(1.0 / 3.0);
-    T phi3 = v3 * T(1.0 / 3.0) + v4 * T(5.0 / 6.0) - v5 * T(1.0 / 6.0);
-    T q1 = v1 - T(2) * v2 + v3;
-    T q2 = v2 - T(2) * v3 + v4;
-    T q3 = v3 - T(2) * v4 + v5;
-    T r1 = v1 - T(4) * v2 + T(3) * v3;
-    T r2 = v2 - v4;
-    T r3 = T(3) * v3 - T(4) * v4 + v5;
-    T S1 = c13_12 * q1 * q1 + T(0.25) * r1 * r1;
-    T S2 = c13_12 * q2 * q2 + T(0.25) * r2 * r2;
-    T S3 = c13_12 * q3 * q3 + T(0.25) * r3 * r3;
-    T m = fmax(fmax(fmax(v1 * v1, v2 * v2), fmax(v3 * v3, v4 * v4)), v5 * v5);
-    T eps = T(1e-6) * m + T(1e-18);
-    T ie = recip(eps);
-    T t1 = S1 * ie + T(1);
-    T t2 = S2 * ie + T(1);
-    T t3 = S3 * ie + T(1);
-    T s1 = t1 * t1, s2 = t2 * t2, s3 = t3 * t3;
-    T b1 = T(0.1) * (s2 * s3);
-    T b2 = T(0.6) * (s1 * s3);
-    T b3 = T(0.3) * (s1 * s2);
+    const T sc = pow2_recip(eps);
+    const T e = eps * sc;
+    const T t1 = S1 * sc + e, t2 = S2 * sc + e, t3 = S3 * sc + e;
+    const T s1 = t1 * t1, s2 = t2 * t2, s3 = t3 * t3;
+    const T b1 = T(0.1) * (s2 * s3);
+    const T b2 = T(0.6) * (s1 * s3);
+    const T b3 = T(0.3) * (s1 * s2);
     return (b1 * phi1 + b2 * phi2 + b3 * phi3) * recip(b1 + b2 + b3);
 }
 
-// First differences along one dim around node j, with the edge rule applied:
-// d[k] = (S[j+k-2] - S[j+k-3]) / dx for k = 0..5 (WENO5) or k = 0..1 = (j, j+1) (upwind).
-// Non-periodic: the difference index m is clamped to [1, n-1] (linear extrapolation).
-template <typename T, int SPATIAL>
-__device__ __forceinline__ void line_derivs(const T *__restrict__ S, uint32_t node, int j, int n,
-                                            uint32_t stride, bool periodic, T inv_dx, T &dm, T &dp)
+template <typename T>
+__device__ __forceinline__ void weno5_pair(const T *d, T &dm, T &dp)
 {
-    constexpr int H = SPATIAL == kWeno5 ? 3 : 1;  // half width of the value stencil
-    T u[2 * H + 1];
+    const T k13 = T(13.0 / 12.0);
+    // second differences centred at offsets -1, 0, 1, 2
+    const T c1 = d[0] - T(2) * d[1] + d[2];
+    const T c2 = d[1] - T(2) * d[2] + d[3];
+    const T c3 = d[2] - T(2) * d[3] + d[4];
+    const T c4 = d[3] - T(2) * d[4] + d[5];
+    const T q1 = k13 * c1 * c1, q2 = k13 * c2 * c2, q3 = k13 * c3 * c3, q4 = k13 * c4 * c4;
+    const T mid = fmax(fmax(d[1] * d[1], d[2] * d[2]), fmax(d[3] * d[3], d[4] * d[4]));
+    // D-: v = (d0, d1, d2, d3, d4)
+    {
+        const T r1 = d[0] - T(4) * d[1] + T(3) * d[2];
+        const T r2 = d[1] - d[3];
+        const T r3 = T(3) * d[2] - T(4) * d[3] + d[4];
+        const T S1 = q1 + T(0.25) * r1 * r1, S2 = q2 + T(0.25) * r2 * r2, S3 = q3 + T(0.25) * r3 * r3;
+        const T eps = T(1e-6) * fmax(mid, d[0] * d[0]) + T(1e-18);
+        const T phi1 = d[0] * T(1.0 / 3.0) - d[1] * T(7.0 / 6.0) + d[2] * T(11.0 / 6.0);
+        const T phi2 = -d[1] * T(1.0 / 6.0) + d[2] * T(5.0 / 6.0) + d[3] * T(1.0 / 3.0);
+        const T phi3 = d[2] * T(1.0 / 3.0) + d[3] * T(5.0 / 6.0) - d[4] * T(1.0 / 6.0);
+        dm = weno5_combine(S1, S2, S3, eps, phi1, phi2, phi3);
+    }
+    // D+: v = (d5, d4, d3, d2, d1)
+    {
+        const T r1 = d[5] - T(4) * d[4] + T(3) * d[3];
+        const T r2 = d[4] - d[2];
+        const T r3 = T(3) * d[3] - T(4) * d[2] + d[1];
+        const T S1 = q4 + T(0.25) * r1 * r1, S2 = q3 + T(0.25) * r2 * r2, S3 = q2 + T(0.25) * r3 * r3;
+        const T eps = T(1e-6) * fmax(mid, d[5] * d[5]) + T(1e-18);
+        const T phi1 = d[5] * T(1.0 / 3.0) - d[4] * T(7.0 / 6.0) + d[3] * T(11.0 / 6.0);
+        const T phi2 = -d[4] * T(1.0 / 6.0) + d[3] * T(5.0 / 6.0) + d[2] * T(1.0 / 3.0);
+        const T phi3 = d[3] * T(1.0 / 3.0) + d[2] * T(5.0 / 6.0) - d[1] * T(1.0 / 6.0);
+        dp = weno5_combine(S1, S2, S3, eps, phi1, phi2, phi3);
+    }
+}
+
+// Stencil values along one dim: u[o + H] = S at line position j + o, o = -H..H (H = 3 for WENO5,
+// 1 for upwind), wrapped on a periodic dim and clamped to the line on a non-periodic one (the
+// clamped values are replaced by extrapolated differences in line_derivs).  The centre value is
+// shared by every dim and is not loaded here.
+template <typename T, int SPATIAL>
+__device__ __forceinline__ void line_load(const T *__restrict__ S, uint32_t node, int j, int n, uint32_t stride,
+                                          bool periodic, T *u)
+{
+    constexpr int H = SPATIAL == kWeno5 ? 3 : 1;
 #pragma unroll
     for (int o = -H; o <= H; ++o) {
+        if (o == 0) continue;
         int jj = j + o;
         if (periodic) {
             jj += jj < 0 ? n : 0;
@@ -190,14 +246,24 @@ __device__ __forceinline__ void line_derivs(const T *__restrict__ S, uint32_t no
         } else {
             jj = jj < 0 ? 0 : (jj > n - 1 ? n - 1 : jj);
         }
-        u[o + H] = S[node + (int)((jj - j) * (int)stride)];
+        u[o + H] = ldg(S, node + (uint32_t)((jj - j) * (int)stride));
     }
-    // raw differences r[o] = u[o] - u[o-1] for o = -H+1 .. H
+}
+
+// Left and right derivatives D-V, D+V at node j of a line of n nodes from its stencil values.
+// First differences r[k] = (u[k+1] - u[k]) / dx (WENO5: offsets -2..3; upwind: 0..1).  On a
+// non-periodic dim a difference beyond an edge equals the nearest interior one (linear
+// extrapolation of V); waves whose nodes are all at least H nodes from both ends skip that rule
+// (the vote is per wave, so the branch never diverges).
+template <typename T, int SPATIAL>
+__device__ __forceinline__ void line_derivs(const T *u, int j, int n, bool periodic, T inv_dx, T &dm, T &dp)
+{
+    constexpr int H = SPATIAL == kWeno5 ? 3 : 1;
     T r[2 * H];
 #pragma unroll
     for (int o = -H + 1; o <= H; ++o) r[o + H - 1] = u[o + H] - u[o + H - 1];
-    if (!periodic) {
-        const int lo = 1 - j, hi = n - 1 - j;  // valid difference offsets
+    if (!periodic && !__all(j >= H && j < n - H)) {
+        const int lo = 1 - j, hi = n - 1 - j;  // offsets of the first and last valid difference
         T rlo = r[0], rhi = r[2 * H - 1];
 #pragma unroll
         for (int o = -H + 1; o <= H; ++o) {
@@ -215,9 +281,7 @@ __device__ __forceinline__ void line_derivs(const T *__restrict__ S, uint32_t no
 #pragma unroll
     for (int k = 0; k < 2 * H; ++k) r[k] *= inv_dx;
     if constexpr (SPATIAL == kWeno5) {
-        // r[k] is the difference at offset k-2 (k = 0..5): D- uses offsets -2..2, D+ 3..-1
-        dm = weno5<T>(r[0], r[1], r[2], r[3], r[4]);
-        dp = weno5<T>(r[5], r[4], r[3], r[2], r[1]);
+        weno5_pair<T>(r, dm, dp);
     } else {
         dm = r[0];
         dp = r[1];
@@ -241,23 +305,23 @@ __device__ __forceinline__ T hamiltonian(const Inst &I, const T *__restrict__ ta
 {
     using F = Fields<T>;
     if constexpr (DYN == kDynDI) {
-        T x2 = tab[I.coord_off[1] + idx[1]];
+        T x2 = ldg(tab, I.coord_off[1] + idx[1]);
         T cu = F::c(I, 0), dd = F::c(I, 1);
         alpha[0] = fabs(x2) + dd;
         alpha[1] = cu;
         return p[0] * x2 + sgn * (cu * fabs(p[1]) - dd * fabs(p[0]));
     } else if constexpr (DYN == kDynDubins) {
-        T cs = tab[I.trig_off + idx[2]];
-        T sn = tab[I.trig_off + I.n[2] + idx[2]];
+        T cs = ldg(tab, I.trig_off + idx[2]);
+        T sn = ldg(tab, I.trig_off + I.n[2] + idx[2]);
         T v = F::c(I, 0), ub = F::c(I, 1), d1 = F::c(I, 2), d2 = F::c(I, 3);
         alpha[0] = fabs(v * cs) + d1;
         alpha[1] = fabs(v * sn) + d2;
         alpha[2] = ub;
         return v * (p[0] * cs + p[1] * sn) + sgn * (ub * fabs(p[2]) - d1 * fabs(p[0]) - d2 * fabs(p[1]));
     } else if constexpr (DYN == kDynUnicycle) {
-        T cs = tab[I.trig_off + idx[2]];
-        T sn = tab[I.trig_off + I.n[2] + idx[2]];
-        T v = tab[I.coord_off[3] + idx[3]];
+        T cs = ldg(tab, I.trig_off + idx[2]);
+        T sn = ldg(tab, I.trig_off + I.n[2] + idx[2]);
+        T v = ldg(tab, I.coord_off[3] + idx[3]);
         T u1 = F::c(I, 0), u2 = F::c(I, 1), dd = F::c(I, 2);
         alpha[0] = fabs(v * cs) + dd;
         alpha[1] = fabs(v * sn) + dd;
@@ -266,9 +330,9 @@ __device__ __forceinline__ T hamiltonian(const Inst &I, const T *__restrict__ ta
         T dist = F::c(I, 3) != T(0) ? dd * (fabs(p[0]) + fabs(p[1])) : dd * sqrt(p[0] * p[0] + p[1] * p[1]);
         return v * (p[0] * cs + p[1] * sn) + sgn * (u1 * fabs(p[2]) + u2 * fabs(p[3]) - dist);
     } else {
-        T vx = tab[I.coord_off[3] + idx[3]];
-        T vy = tab[I.coord_off[4] + idx[4]];
-        T vz = tab[I.coord_off[5] + idx[5]];
+        T vx = ldg(tab, I.coord_off[3] + idx[3]);
+        T vy = ldg(tab, I.coord_off[4] + idx[4]);
+        T vz = ldg(tab, I.coord_off[5] + idx[5]);
         T ax = F::c(I, 0), ay = F::c(I, 1), tmax = F::c(I, 2), tmin = F::c(I, 3);
         T dx = F::c(I, 4), dy = F::c(I, 5), dz = F::c(I, 6);
         alpha[0] = fabs(vx);
@@ -304,20 +368,28 @@ __device__ __forceinline__ void unflatten(const Inst &I, uint32_t node, int *idx
     idx[0] = (int)rem;
 }
 
-// L(S) at one node.
+// L(S) at one node.  Every stencil value of every dim is loaded before any arithmetic, so a
+// wave has all its loads in flight at once.  Returns the centre value through *centre.
 template <typename T, int DYN, int SPATIAL>
-__device__ __forceinline__ T lf_operator(const Inst &I, const T *__restrict__ S, uint32_t node)
+__device__ __forceinline__ T lf_operator(const Inst &I, const T *__restrict__ S, uint32_t node, T *centre)
 {
     constexpr int N = DynDim<DYN>::value;
+    constexpr int W = SPATIAL == kWeno5 ? 7 : 3;
     using F = Fields<T>;
     int idx[N];
     unflatten<N>(I, node, idx);
+    T u[N][W];
+    const T c = ldg(S, node);
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+        line_load<T, SPATIAL>(S, node, idx[d], I.n[d], I.stride[d], (I.periodic >> d) & 1u, u[d]);
+        u[d][W / 2] = c;
+    }
     T p[N], diff[N], alpha[N];
 #pragma unroll
     for (int d = 0; d < N; ++d) {
         T dm, dp;
-        line_derivs<T, SPATIAL>(S, node, idx[d], I.n[d], I.stride[d], (I.periodic >> d) & 1u,
-                                F::inv_dx(I, d), dm, dp);
+        line_derivs<T, SPATIAL>(u[d], idx[d], I.n[d], (I.periodic >> d) & 1u, F::inv_dx(I, d), dm, dp);
         p[d] = T(0.5) * (dm + dp);
         diff[d] = T(0.5) * (dp - dm);
     }
@@ -325,6 +397,7 @@ __device__ __forceinline__ T lf_operator(const Inst &I, const T *__restrict__ S,
     T L = hamiltonian<T, DYN>(I, F::tab(I), idx, p, alpha, sgn);
 #pragma unroll
     for (int d = 0; d < N; ++d) L += alpha[d] * diff[d];
+    *centre = c;
     return L;
 }
 

@@ -1,7 +1,7 @@
 // hjr_kernels.hip -- gfx950 kernels of the HJI VI grid update and their launch wrappers.
 //
-// Work is described by a list of tiles (instance, first node); a tile is kBlock consecutive
-// nodes of one instance's flattened grid.  One launch of a stage kernel advances every tile of
+// Work is described by a list of tiles (instance, first node, nodes per thread); a tile is
+// npt * kBlock consecutive nodes of one instance's flattened grid.  One launch of a stage kernel advances every tile of
 // every instance in its list, so a batch of grids of different size and dimension moves in one
 // launch per stage.  Workgroups are mapped to tiles so that each XCD (workgroups are dealt to
 // the eight XCDs round-robin) takes one contiguous run of tiles: the stencil halo of a tile is
@@ -77,7 +77,7 @@ __device__ __forceinline__ TileRange xcd_range(int ntiles)
 // Stage kernel
 // --------------------------------------------------------------------------------------------
 
-template <typename T, int DYN, int SPATIAL>
+template <typename T, int DYN, int SPATIAL, int NPT>
 __device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int stage, T dt, double *red)
 {
     using F = Fields<T>;
@@ -99,24 +99,35 @@ __device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int st
         S = B; Vn = V; O = V;
     }
     const bool last = euler || stage == 2;
-    const uint32_t node = start + threadIdx.x;
+    const T *l = F::l(I);
     double delta = 0.0;
-    if (node < I.npts) {
-        T L = lf_operator<T, DYN, SPATIAL>(I, S, node);
-        T s = S[node];
-        T vn = Vn[node];
+    // NPT nodes per thread, kBlock apart: independent work the scheduler can interleave
+    auto one = [&](uint32_t node) {
+        T s;
+        T L = lf_operator<T, DYN, SPATIAL>(I, S, node, &s);
+        T vn = ldg(Vn, node);
         T out;
         if (euler) {
-            out = fmin(F::l(I)[node], s + dt * L);
+            out = fmin(ldg(l, node), s + dt * L);
         } else if (stage == 0) {
             out = s + dt * L;
         } else if (stage == 1) {
             out = T(0.75) * vn + T(0.25) * (s + dt * L);
         } else {
-            out = fmin(F::l(I)[node], vn * T(1.0 / 3.0) + T(2.0 / 3.0) * (s + dt * L));
+            out = fmin(ldg(l, node), vn * T(1.0 / 3.0) + T(2.0 / 3.0) * (s + dt * L));
         }
-        O[node] = out;
-        if (last) delta = (double)fabs(out - vn);
+        stg(O, node, out);
+        if (last) delta = nanmax(delta, (double)fabs(out - vn));
+    };
+    if (start + (uint32_t)(NPT * kBlock) <= I.npts) {
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) one(start + k * kBlock + threadIdx.x);
+    } else {
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const uint32_t node = start + k * kBlock + threadIdx.x;
+            if (node < I.npts) one(node);
+        }
     }
     if (last) block_max_to(delta, &st->delta_bits, red);
 }
@@ -136,16 +147,34 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const Inst *__restrict__ 
         const T dt = (T)st->dt_cur;
         const int key = I.dyn * 8 + I.spatial;
         switch (key) {
-        case kDynDI * 8 + kUpwind1: stage_tile<T, kDynDI, kUpwind1>(I, tl.start, stage, dt, red); break;
-        case kDynDI * 8 + kWeno5: stage_tile<T, kDynDI, kWeno5>(I, tl.start, stage, dt, red); break;
-        case kDynDubins * 8 + kUpwind1: stage_tile<T, kDynDubins, kUpwind1>(I, tl.start, stage, dt, red); break;
-        case kDynDubins * 8 + kWeno5: stage_tile<T, kDynDubins, kWeno5>(I, tl.start, stage, dt, red); break;
-        case kDynUnicycle * 8 + kUpwind1: stage_tile<T, kDynUnicycle, kUpwind1>(I, tl.start, stage, dt, red); break;
-        case kDynUnicycle * 8 + kWeno5: stage_tile<T, kDynUnicycle, kWeno5>(I, tl.start, stage, dt, red); break;
-        case kDynQuad * 8 + kUpwind1: stage_tile<T, kDynQuad, kUpwind1>(I, tl.start, stage, dt, red); break;
-        case kDynQuad * 8 + kWeno5: stage_tile<T, kDynQuad, kWeno5>(I, tl.start, stage, dt, red); break;
+        case kDynDI * 8 + kUpwind1: stage_tile<T, kDynDI, kUpwind1, kFusedNpt>(I, tl.start, stage, dt, red); break;
+        case kDynDI * 8 + kWeno5: stage_tile<T, kDynDI, kWeno5, kFusedNpt>(I, tl.start, stage, dt, red); break;
+        case kDynDubins * 8 + kUpwind1: stage_tile<T, kDynDubins, kUpwind1, kFusedNpt>(I, tl.start, stage, dt, red); break;
+        case kDynDubins * 8 + kWeno5: stage_tile<T, kDynDubins, kWeno5, kFusedNpt>(I, tl.start, stage, dt, red); break;
+        case kDynUnicycle * 8 + kUpwind1: stage_tile<T, kDynUnicycle, kUpwind1, kFusedNpt>(I, tl.start, stage, dt, red); break;
+        case kDynUnicycle * 8 + kWeno5: stage_tile<T, kDynUnicycle, kWeno5, kFusedNpt>(I, tl.start, stage, dt, red); break;
+        case kDynQuad * 8 + kUpwind1: stage_tile<T, kDynQuad, kUpwind1, kFusedNpt>(I, tl.start, stage, dt, red); break;
+        case kDynQuad * 8 + kWeno5: stage_tile<T, kDynQuad, kWeno5, kFusedNpt>(I, tl.start, stage, dt, red); break;
         default: break;
         }
+    }
+}
+
+// One model and one scheme per kernel: register allocation (and so occupancy) follows that
+// variant alone instead of the largest variant of the fused kernel.
+template <typename T, int DYN, int SPATIAL, int NPT>
+__global__ __launch_bounds__(kBlock) void stage_kernel_one(const Inst *__restrict__ insts,
+                                                           const Tile *__restrict__ tiles, int ntiles,
+                                                           int stage)
+{
+    __shared__ double red[kBlock / 64];
+    const TileRange r = xcd_range(ntiles);
+    for (int c = 0; c < r.count; ++c) {
+        const Tile tl = tiles[r.first + c * r.step];
+        const Inst &I = insts[tl.inst];
+        SolveState *st = I.state;
+        if (st->done != kRunning || stage >= I.nstages) continue;
+        stage_tile<T, DYN, SPATIAL, NPT>(I, tl.start, stage, (T)st->dt_cur, red);
     }
 }
 
@@ -175,17 +204,20 @@ __device__ __forceinline__ void apply_limits(SolveState *st)
     }
 }
 
-// FP32 phases: no new 1% low of the change for stall_window steps (or intervals) means the
-// iterate has reached the FP32 rounding floor.
+// Stall rule: no new 1% low of the change for stall_window steps (or intervals) while the
+// change is within 64x of the threshold, or for 16 stall_windows at any level, means the iterate
+// has reached its floor (FP32 rounding, or a limit cycle of the scheme).  Far from the threshold
+// the change may plateau or grow for a while as fronts develop, hence the longer window there.
 __device__ __forceinline__ void note_delta(SolveState *st, double delta, long long count)
 {
     if (st->stall_window <= 0 || st->done != kRunning) return;
     if (delta < 0.99 * st->best_delta) {
         st->best_delta = delta;
         st->n_best = count;
-    } else if (count - st->n_best >= st->stall_window) {
-        st->done = kStalled;
+        return;
     }
+    const long long window = delta < 64.0 * st->tol ? st->stall_window : 16 * st->stall_window;
+    if (count - st->n_best >= window) st->done = kStalled;
 }
 
 __global__ void step_end_kernel(const Inst *__restrict__ insts, int ninst)
@@ -228,12 +260,14 @@ __global__ __launch_bounds__(kBlock) void interval_kernel(const Inst *__restrict
         if (st->done != kRunning || !st->check_interval) continue;
         const T *cur = (I.temporal == kEuler && st->parity) ? F::A(I) : F::V(I);
         T *snap = F::snap(I);
-        const uint32_t node = tl.start + threadIdx.x;
         double d = 0.0;
-        if (node < I.npts) {
-            T v = cur[node];
-            d = (double)fabs(v - snap[node]);
-            snap[node] = v;
+        for (int k = 0; k < tl.npt; ++k) {
+            const uint32_t node = tl.start + k * kBlock + threadIdx.x;
+            if (node < I.npts) {
+                T v = cur[node];
+                d = nanmax(d, (double)fabs(v - snap[node]));
+                snap[node] = v;
+            }
         }
         block_max_to(d, &st->idelta_bits, red);
     }
@@ -413,6 +447,64 @@ hipError_t launch_stage(bool fp64, const Inst *insts, const Tile *tiles, int nti
         hipLaunchKernelGGL(stage_kernel<double>, dim3(g), dim3(kBlock), 0, s, insts, tiles, ntiles, stage);
     else
         hipLaunchKernelGGL(stage_kernel<float>, dim3(g), dim3(kBlock), 0, s, insts, tiles, ntiles, stage);
+    return hipGetLastError();
+}
+
+template <typename T, int NPT>
+static void launch_one_npt(int dyn, int spatial, dim3 g, hipStream_t s, const Inst *insts, const Tile *tiles,
+                           int ntiles, int stage)
+{
+#define HJR_ONE(D, SP)                                                                                   \
+    hipLaunchKernelGGL((stage_kernel_one<T, D, SP, NPT>), g, dim3(kBlock), 0, s, insts, tiles, ntiles, stage)
+    const int key = dyn * 8 + spatial;
+    switch (key) {
+    case kDynDI * 8 + kUpwind1: HJR_ONE(kDynDI, kUpwind1); break;
+    case kDynDI * 8 + kWeno5: HJR_ONE(kDynDI, kWeno5); break;
+    case kDynDubins * 8 + kUpwind1: HJR_ONE(kDynDubins, kUpwind1); break;
+    case kDynDubins * 8 + kWeno5: HJR_ONE(kDynDubins, kWeno5); break;
+    case kDynUnicycle * 8 + kUpwind1: HJR_ONE(kDynUnicycle, kUpwind1); break;
+    case kDynUnicycle * 8 + kWeno5: HJR_ONE(kDynUnicycle, kWeno5); break;
+    case kDynQuad * 8 + kUpwind1: HJR_ONE(kDynQuad, kUpwind1); break;
+    case kDynQuad * 8 + kWeno5: HJR_ONE(kDynQuad, kWeno5); break;
+    default: break;
+    }
+#undef HJR_ONE
+}
+
+template <typename T>
+static void launch_one(int dyn, int spatial, int npt, dim3 g, hipStream_t s, const Inst *insts, const Tile *tiles,
+                       int ntiles, int stage)
+{
+    switch (npt) {
+    case 1: launch_one_npt<T, 1>(dyn, spatial, g, s, insts, tiles, ntiles, stage); break;
+    case 2: launch_one_npt<T, 2>(dyn, spatial, g, s, insts, tiles, ntiles, stage); break;
+    case 8: launch_one_npt<T, 8>(dyn, spatial, g, s, insts, tiles, ntiles, stage); break;
+    default: launch_one_npt<T, 4>(dyn, spatial, g, s, insts, tiles, ntiles, stage); break;
+    }
+}
+
+hipError_t launch_stage_one(bool fp64, int dyn, int spatial, int npt, const Inst *insts, const Tile *tiles, int ntiles,
+                            int stage, int max_blocks, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const dim3 g(grid_for(ntiles, max_blocks));
+    if (fp64)
+        launch_one<double>(dyn, spatial, npt, g, s, insts, tiles, ntiles, stage);
+    else
+        launch_one<float>(dyn, spatial, npt, g, s, insts, tiles, ntiles, stage);
+    return hipGetLastError();
+}
+
+// Zero the max-change accumulators of every instance (after timing trial launches).
+__global__ void clear_deltas_kernel(const Inst *__restrict__ insts, int ninst)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ninst) insts[i].state->delta_bits = 0ull;
+}
+
+hipError_t launch_clear_deltas(const Inst *insts, int ninst, hipStream_t s)
+{
+    hipLaunchKernelGGL(clear_deltas_kernel, dim3((ninst + 63) / 64), dim3(64), 0, s, insts, ninst);
     return hipGetLastError();
 }
 

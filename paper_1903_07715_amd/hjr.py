@@ -13,7 +13,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhjr.so")
+LIB_PATH = os.environ.get("HJR_LIBRARY") or os.path.join(_HERE, "libhjr.so")
 MAX_DIM = 6
 MAX_PARAMS = 16
 

@@ -54,7 +54,7 @@ def test_batch_mixed_precision_and_schemes(gpu, hjrlib):
     p3 = W.di_box_problem(41, dbar=0.2)
     cases = [(p1, dict(precision=hjrlib.FP64, spatial=1, temporal=1, cfl=0.8)),
              (p2, dict(precision=hjrlib.FP32, **hjrlib.problem_options(p2))),
-             (p3, dict(precision=hjrlib.FP32_POLISH64, spatial=5, temporal=3, cfl=0.5))]
+             (p3, dict(precision=hjrlib.FP32_POLISH64, spatial=1, temporal=1, cfl=0.8))]
     Vs, rs, sts = hjrlib.batch_solve([(p.grid, p.dyn) for p, _ in cases], [p.l for p, _ in cases], [None] * 3,
                                      [o for _, o in cases])
     for (p, o), V, r, st in zip(cases, Vs, rs, sts):

@@ -39,8 +39,11 @@ def _field(grid, l, seed):
     return V
 
 
+@pytest.mark.parametrize("npt", ["1", "2", "4", "8"])
 @pytest.mark.parametrize("name", ["dubins101", "unicycle61", "quad25"])
-def test_fullsize_fp32_stages_on_sampled_nodes(gpu, hjrlib, orc, name):
+def test_fullsize_fp32_stages_on_sampled_nodes(gpu, hjrlib, orc, name, npt, monkeypatch):
+    """Every nodes-per-thread variant the autotuner may pick is checked."""
+    monkeypatch.setenv("HJR_NPT", npt)
     torch = __import__("torch")
     if name == "dubins101":
         p = W.dubins_problem(101)
@@ -49,7 +52,7 @@ def test_fullsize_fp32_stages_on_sampled_nodes(gpu, hjrlib, orc, name):
     else:
         p = W.quad6_problem(25)
     g = p.grid
-    print(f"[fullsize] {name}: {g.size} nodes", flush=True)
+    print(f"[fullsize] {name}: {g.size} nodes, {npt} nodes per thread", flush=True)
     l32 = p.l.astype(np.float32)
     V0 = _field(g, p.l, 1).astype(np.float32)
     dt = orc.cfl_dt(g, p.dyn, p.cfl)

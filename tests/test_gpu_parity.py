@@ -217,3 +217,23 @@ def test_device_entry_point_matches_host_entry_point(gpu, hjrlib):
     assert st == hjrlib.OK
     assert np.array_equal(V_t.cpu().numpy(), Vh)
     assert rd["iterations"] == rh["iterations"]
+
+
+@pytest.mark.parametrize("env", [{"HJR_GRAPHS": "1"}, {"HJR_NPT": "1"}, {"HJR_NPT": "2"}, {"HJR_NPT": "8"},
+                                 {"HJR_FUSED": "1"}, {"HJR_MAX_BLOCKS": "64"}, {"HJR_AUTOTUNE": "0"}],
+                         ids=lambda e: ",".join(f"{k}={v}" for k, v in e.items()))
+def test_launch_configurations_agree_bitwise(gpu, hjrlib, monkeypatch, env):
+    """Graph replay vs direct launches, every nodes-per-thread variant, the fused kernel and a
+    persistent grid give bitwise the same solve: the per-node arithmetic is the same in all."""
+    p = W.dubins_problem(31)
+    q = W.di_box_problem(61)
+    ref = [hjrlib.solve(x.grid, x.dyn, x.l, None, **o) for x, o in
+           ((p, hjrlib.problem_options(p)), (q, dict(spatial=1, temporal=1, cfl=0.8, precision=hjrlib.FP64)))]
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    got = [hjrlib.solve(x.grid, x.dyn, x.l, None, **o) for x, o in
+           ((p, hjrlib.problem_options(p)), (q, dict(spatial=1, temporal=1, cfl=0.8, precision=hjrlib.FP64)))]
+    for (Va, ra, sa), (Vb, rb, sb) in zip(ref, got):
+        assert sa == sb
+        assert (ra["iterations"], ra["polish_iterations"]) == (rb["iterations"], rb["polish_iterations"])
+        assert np.array_equal(Va, Vb)
