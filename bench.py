@@ -65,6 +65,11 @@ def parse():
     ap.add_argument("--n", type=int, default=101, help="grid side (default 101)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["dubins", "batch", "serve"], default="dubins",
+                    help="dubins: the headline single-solve benchmark; batch: the 64-instance mixed batch; "
+                         "serve: a Poisson request stream through the serving context, warm vs cold")
+    ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
+    ap.add_argument("--quad-n", type=int, default=15, help="serve: grid side of the 6-D quadrotor requests")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run 5 plain device copies of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -116,6 +121,12 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.workload == "batch":
+        bench_batch(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
         return
     import torch
 
@@ -226,6 +237,140 @@ def main():
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(p, npts, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def bench_batch(args):
+    """64 seeded mixed instances (double integrator 51^2-201^2, Dubins 41^3-121^3), FP32,
+    device-resident, advanced together by the serving context (every stage of every instance
+    in the same launches), against the same solves one after another."""
+    import torch
+
+    from paper_1903_07715_amd import hjr
+    from paper_1903_07715_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    probs = W.batch_problems(64)
+    ls = [torch.tensor(p.l, device=dev) for p in probs]
+    outs = [torch.empty_like(l) for l in ls]
+    opts = [hjr.problem_options(p, precision=hjr.FP32, max_iter=20000) for p in probs]
+    npts = sum(p.grid.size for p in probs)
+    log(f"batch: {len(probs)} instances, {npts} nodes")
+    torch.cuda.synchronize()
+
+    def batched():
+        with hjr.Context(0) as ctx:
+            ts = [ctx.submit(p.grid, p.dyn, l, None, V, **o) for p, l, V, o in zip(probs, ls, outs, opts)]
+            ctx.drain()
+            res = [ctx.poll(t) for t in ts]
+            stats = ctx.stats()
+        return res, stats
+
+    batched()  # warm-up (tuning, first-touch allocation)
+    t0 = time.perf_counter()
+    res, stats = batched()
+    bt = time.perf_counter() - t0
+    upd = sum((r["iterations"] + r["polish_iterations"]) * p.grid.size for (_, r), p in zip(res, probs))
+    log(f"batched: {bt:.3f} s, {stats['chunks']} chunks, {stats['launches']} launches")
+    t0 = time.perf_counter()
+    for p, l, V, o in zip(probs, ls, outs, opts):
+        hjr.solve_device(p.grid, p.dyn, l, None, V, **o)
+    torch.cuda.synchronize()
+    st = time.perf_counter() - t0
+    log(f"one by one: {st:.3f} s")
+    print(json.dumps({"workload": "batch64-di-dubins-fp32", "instances": len(probs), "nodes": npts,
+                      "batched_seconds": bt, "sequential_seconds": st, "batched_solves_per_s": len(probs) / bt,
+                      "sequential_solves_per_s": len(probs) / st, "speedup": st / bt,
+                      "grid_point_updates_per_s": upd / bt,
+                      "statuses": sorted(set(s for s, _ in res)), "launches": stats["launches"],
+                      "chunks": stats["chunks"]}), flush=True)
+
+
+def bench_serve(args):
+    """Poisson stream of reachability requests whose parameters change (quadrotor mass and
+    disturbance, Dubins and double-integrator control and disturbance bounds, unicycle
+    disturbance), through the serving context, warm-started from resident prior solutions vs
+    cold, on the same arrival trace."""
+    import random
+
+    import torch
+
+    from paper_1903_07715_amd import hjr, serving
+    from paper_1903_07715_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    rng = random.Random(W.SEED)
+    kinds = {}
+    qn = args.quad_n
+    quad = W.quad6_problem(qn)
+    kinds["quad6"] = (quad, torch.tensor(quad.l, device=dev))
+    dub = W.dubins_problem(61)
+    kinds["dubins3"] = (dub, torch.tensor(dub.l, device=dev))
+    uni = W.unicycle_problem(31)
+    kinds["unicycle4"] = (uni, torch.tensor(uni.l, device=dev))
+    di = W.di_box_problem(101)
+    kinds["di2"] = (di, torch.tensor(di.l, device=dev))
+
+    def make(kind, arrival):
+        p, l_t = kinds[kind]
+        if kind == "quad6":
+            m, db = rng.uniform(1.0, 1.4), rng.uniform(0.2, 0.8)
+            dyn, key = W.quad6(m=m, dbar=(db, db, db)), (m, db)
+            dom = lambda a, b: a[0] <= b[0] and a[1] <= b[1]       # lighter, calmer prior
+        elif kind == "dubins3":
+            ub, db = rng.uniform(1.0, 2.0), rng.uniform(0.0, 0.2)
+            dyn, key = W.dubins3(1.0, ub, db), (-ub, db)
+            dom = lambda a, b: a[0] <= b[0] and a[1] <= b[1]       # more control, less disturbance
+        elif kind == "unicycle4":
+            db = rng.uniform(0.0, 0.2)
+            dyn, key = W.unicycle4(1.0, 0.5, db), (db,)
+            dom = lambda a, b: a[0] <= b[0]
+        else:
+            ub, db = rng.uniform(0.5, 2.0), rng.uniform(0.0, 0.2)
+            dyn, key = W.double_integrator(ub, 1.0, db), (-ub, db)
+            dom = lambda a, b: a[0] <= b[0] and a[1] <= b[1]
+        opts = hjr.problem_options(p, precision=hjr.FP32_POLISH64, max_iter=20000)
+        return serving.Request(kind=kind, grid=p.grid, dyn=dyn, key=key, dominates=dom, l_dev=l_t, opts=opts,
+                               arrival=arrival)
+
+    mix = ["quad6"] * 4 + ["dubins3"] * 2 + ["unicycle4"] * 2 + ["di2"] * 2
+    # calibration: one cold solve of each kind alone gives the mean service time
+    svc = {}
+    for kind in kinds:
+        r = make(kind, 0.0)
+        V = torch.empty_like(r.l_dev)
+        t0 = time.perf_counter()
+        hjr.solve_device(r.grid, r.dyn, r.l_dev, None, V, **r.opts)
+        torch.cuda.synchronize()
+        svc[kind] = time.perf_counter() - t0
+        log(f"calibration {kind}: {svc[kind]:.3f} s")
+    mean_svc = sum(svc[k] for k in mix) / len(mix)
+    rate = 0.7 / mean_svc
+    log(f"arrival rate {rate:.2f}/s (0.7 x one-at-a-time capacity)")
+    rng.seed(W.SEED + 1)
+    t = 0.0
+    trace = []
+    for _ in range(args.requests):
+        t += rng.expovariate(rate)
+        trace.append((rng.choice(mix), t))
+    out = {}
+    for warm in (False, True):
+        rng.seed(W.SEED + 2)
+        reqs = [make(kind, at) for kind, at in trace]
+        with hjr.Context(0) as ctx:
+            srv = serving.WarmStartServer(ctx, warm=warm)
+            srv.run(reqs, torch, dev)
+            stats = ctx.stats()
+        st = serving.latency_stats(reqs)
+        st["steps"] = sum(r.result.get("iterations", 0) + r.result.get("polish_iterations", 0) for r in reqs)
+        st["statuses"] = sorted(set(r.status for r in reqs))
+        st["warm_started"] = sum(1 for r in reqs if r.warm_from is not None)
+        st["hbm_peak_bytes"] = stats["bytes_peak"]
+        out["warm" if warm else "cold"] = st
+        log(f"{'warm' if warm else 'cold'}: {st}")
+    print(json.dumps({"workload": f"serve-quad6-{qn}^6-dubins61^3-unicycle31^4-di101^2", "requests": args.requests,
+                      "arrival_rate_per_s": rate, "cold": out["cold"], "warm": out["warm"],
+                      "warm_vs_cold_solves_per_s": out["warm"]["solves_per_s"] / out["cold"]["solves_per_s"]}),
+          flush=True)
 
 
 if __name__ == "__main__":

@@ -1433,7 +1433,7 @@ struct hjr_ctx {
     hjr_status fatal = HJR_OK;
     std::string fatal_msg;
     std::thread worker;
-    int steps_per_chunk = 4;
+    int steps_per_chunk = 8;
 
     void loop()
     {
