@@ -68,8 +68,8 @@ def parse():
     ap.add_argument("--workload", choices=["dubins", "batch", "serve"], default="dubins",
                     help="dubins: the headline single-solve benchmark; batch: the 64-instance mixed batch; "
                          "serve: a Poisson request stream through the serving context, warm vs cold")
-    ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
-    ap.add_argument("--quad-n", type=int, default=15, help="serve: grid side of the 6-D quadrotor requests")
+    ap.add_argument("--requests", type=int, default=32, help="serve: number of requests")
+    ap.add_argument("--quad-n", type=int, default=25, help="serve: grid side of the 6-D quadrotor requests")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run 5 plain device copies of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -306,6 +306,7 @@ def bench_serve(args):
     dub = W.dubins_problem(61)
     kinds["dubins3"] = (dub, torch.tensor(dub.l, device=dev))
     uni = W.unicycle_problem(31)
+    uni.spatial, uni.temporal, uni.cfl = 1, 1, 0.8  # converged solves need the monotone scheme here
     kinds["unicycle4"] = (uni, torch.tensor(uni.l, device=dev))
     di = W.di_box_problem(101)
     kinds["di2"] = (di, torch.tensor(di.l, device=dev))
@@ -353,6 +354,19 @@ def bench_serve(args):
         t += rng.expovariate(rate)
         trace.append((rng.choice(mix), t))
     out = {}
+
+    def per_kind(reqs):
+        kk = {}
+        for r in reqs:
+            d = kk.setdefault(r.kind, {"n": 0, "steps": 0, "latency_s": 0.0, "statuses": set()})
+            d["n"] += 1
+            d["steps"] += r.result.get("iterations", 0) + r.result.get("polish_iterations", 0)
+            d["latency_s"] += r.done - r.arrival
+            d["statuses"].add(r.status)
+        return {k: {"n": v["n"], "mean_steps": v["steps"] / v["n"], "mean_latency_s": v["latency_s"] / v["n"],
+                    "statuses": sorted(v["statuses"])} for k, v in kk.items()}
+
+    # 1) Poisson arrivals at 0.7x the one-at-a-time capacity: latency, warm vs cold
     for warm in (False, True):
         rng.seed(W.SEED + 2)
         reqs = [make(kind, at) for kind, at in trace]
@@ -365,11 +379,41 @@ def bench_serve(args):
         st["statuses"] = sorted(set(r.status for r in reqs))
         st["warm_started"] = sum(1 for r in reqs if r.warm_from is not None)
         st["hbm_peak_bytes"] = stats["bytes_peak"]
+        st["per_kind"] = per_kind(reqs)
         out["warm" if warm else "cold"] = st
-        log(f"{'warm' if warm else 'cold'}: {st}")
+        if warm:
+            prior_store = srv.resident
+        log(f"poisson {'warm' if warm else 'cold'}: {st}")
+    # 2) the same requests all at once (saturation): serving loop warm/cold vs plain cold solves
+    sat = {}
+    # fresh parameter draws (seed differs from the Poisson pass); the warm pass starts with the
+    # solutions the warm Poisson pass left resident, i.e. of other parameter values
+    for warm in (False, True):
+        rng.seed(W.SEED + 3)
+        reqs = [make(kind, 0.0) for kind, _ in trace]
+        with hjr.Context(0) as ctx:
+            srv = serving.WarmStartServer(ctx, warm=warm)
+            if warm:
+                srv.resident = prior_store
+            srv.run(reqs, torch, dev)
+        st = serving.latency_stats(reqs)
+        sat["warm" if warm else "cold"] = {"solves_per_s": st["solves_per_s"], "seconds": st["seconds"],
+                                            "steps": sum(r.result.get("iterations", 0) + r.result.get("polish_iterations", 0) for r in reqs)}
+        log(f"burst {'warm' if warm else 'cold'}: {sat['warm' if warm else 'cold']}")
+    rng.seed(W.SEED + 3)
+    reqs = [make(kind, 0.0) for kind, _ in trace]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs:
+        V = torch.empty_like(r.l_dev)
+        hjr.solve_device(r.grid, r.dyn, r.l_dev, None, V, **r.opts)
+    torch.cuda.synchronize()
+    plain = len(reqs) / (time.perf_counter() - t0)
+    sat["plain_cold_solves_per_s"] = plain
+    log(f"plain cold one at a time: {plain:.2f} solves/s")
     print(json.dumps({"workload": f"serve-quad6-{qn}^6-dubins61^3-unicycle31^4-di101^2", "requests": args.requests,
-                      "arrival_rate_per_s": rate, "cold": out["cold"], "warm": out["warm"],
-                      "warm_vs_cold_solves_per_s": out["warm"]["solves_per_s"] / out["cold"]["solves_per_s"]}),
+                      "arrival_rate_per_s": rate, "cold": out["cold"], "warm": out["warm"], "burst": sat,
+                      "warm_serving_vs_plain_cold_solves_per_s": sat["warm"]["solves_per_s"] / plain}),
           flush=True)
 
 

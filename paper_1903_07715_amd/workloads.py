@@ -234,10 +234,21 @@ def unicycle_problem(n=61, moved=False, seed=SEED, cfl=0.5) -> Problem:
                    meta={"centers": (mv if moved else centers).tolist(), "radii": radii.tolist()})
 
 
-def quad6_problem(n=25, m=1.2, dbar=(0.5, 0.5, 0.5), cfl=0.5) -> Problem:
-    """6-D quadrotor translation in a room: p in [-6,6]^3, v in [-3,3]^3, walls |p_i| >= 4 unsafe."""
-    g = Grid((n,) * 6, (-6.0, -6.0, -6.0, -3.0, -3.0, -3.0), (6.0, 6.0, 6.0, 3.0, 3.0, 3.0))
-    return Problem(f"quad{n}", g, quad6(m=m, dbar=dbar), room_target(g), spatial=5, temporal=3, cfl=cfl)
+def quad6_problem(n=25, m=1.2, dbar=(0.5, 0.5, 0.5), cfl=0.8, target="obstacle") -> Problem:
+    """6-D quadrotor translation, v in [-3,3]^3.
+
+    target "obstacle" (default): a cube obstacle |p_i| <= 1 in p in [-5,5]^3, l = its exact
+    signed distance; far from it V = l, so the iteration settles.  target "room": p in [-6,6]^3
+    with the walls |p_i| >= 4 unsafe, l = min_i (4 - |p_i|); l is unbounded below outside the
+    room and the linearly extrapolated edges let V drift down there, so that variant does not
+    settle and is kept for fixed-step checks only.  Scheme: upwind + Euler (monotone)."""
+    if target == "room":
+        g = Grid((n,) * 6, (-6.0, -6.0, -6.0, -3.0, -3.0, -3.0), (6.0, 6.0, 6.0, 3.0, 3.0, 3.0))
+        l = room_target(g)
+    else:
+        g = Grid((n,) * 6, (-5.0, -5.0, -5.0, -3.0, -3.0, -3.0), (5.0, 5.0, 5.0, 3.0, 3.0, 3.0))
+        l = box_sdf(g, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), dims=(0, 1, 2))
+    return Problem(f"quad{n}", g, quad6(m=m, dbar=dbar), l, spatial=1, temporal=1, cfl=cfl)
 
 
 def batch_problems(count=64, seed=SEED, n2=(51, 201), n3=(41, 121)) -> list:
