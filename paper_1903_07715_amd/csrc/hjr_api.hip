@@ -432,10 +432,14 @@ static SolveState initial_state(const Request &r)
 
 // --------------------------------------------------------------------------------------------
 // Autotuner: nodes per thread of the stage kernels, per (precision, model, scheme, size class).
-// A choice is found by timing trial launches on the instances at hand and is kept for the rest
-// of the process; with HJR_TUNE_CACHE=<file> choices are also read from and appended to a
-// small JSON file, so later processes skip the trials.
+// The per-node arithmetic is identical for every candidate (results are bitwise equal), so the
+// tuner explores on the real solve: successive chunks of steps run with successive candidates,
+// the median duration of each candidate's stage launches is recorded, and once every candidate
+// has been timed the fastest is used from then on, for the rest of the process.  With
+// HJR_TUNE_CACHE=<file> the choices are also kept in a small JSON file for later processes.
 // --------------------------------------------------------------------------------------------
+
+static const int kNptCandidates[] = {4, 2, 8, 1};
 
 class Tuner {
 public:
@@ -452,29 +456,51 @@ public:
         snprintf(buf, sizeof buf, "fp%d_dyn%d_sp%d_n2^%d", prec ? 64 : 32, dyn, spatial, b);
         return buf;
     }
-    int lookup(const std::string &k)
+    // The chosen nodes-per-thread, or 0 while candidates remain untimed.
+    int choice(const std::string &k)
     {
         std::lock_guard<std::mutex> g(mu_);
         load_file();
-        auto it = map_.find(k);
-        return it == map_.end() ? 0 : it->second;
+        auto it = chosen_.find(k);
+        return it == chosen_.end() ? 0 : it->second;
     }
-    void store(const std::string &k, int npt)
+    // The next candidate to time for k.
+    int next_candidate(const std::string &k)
     {
         std::lock_guard<std::mutex> g(mu_);
-        map_[k] = npt;
+        auto &m = timed_[k];
+        for (int c : kNptCandidates)
+            if (!m.count(c)) return c;
+        return kNptCandidates[0];
+    }
+    void record(const std::string &k, int npt, double us)
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        auto &m = timed_[k];
+        m[npt] = m.count(npt) ? std::min(m[npt], us) : us;
+        for (int c : kNptCandidates)
+            if (!m.count(c)) return;
+        int best = kNptCandidates[0];
+        for (int c : kNptCandidates)
+            if (m[c] < 0.98 * m[best]) best = c;  // ties go to the earlier candidate
+        chosen_[k] = best;
+        save_file();
+    }
+
+private:
+    void save_file()
+    {
         const char *path = getenv("HJR_TUNE_CACHE");
         if (!path || !*path) return;
         FILE *f = fopen(path, "w");
         if (!f) return;
         fprintf(f, "{\n");
         size_t i = 0;
-        for (auto &kv : map_) fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < map_.size() ? "," : "");
+        for (auto &kv : chosen_)
+            fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < chosen_.size() ? "," : "");
         fprintf(f, "}\n");
         fclose(f);
     }
-
-private:
     void load_file()
     {
         if (loaded_) return;
@@ -488,12 +514,13 @@ private:
             char k[128];
             int v = 0;
             if (sscanf(line, " \"%127[^\"]\" : %d", k, &v) == 2 && (v == 1 || v == 2 || v == 4 || v == 8))
-                map_[k] = v;
+                chosen_[k] = v;
         }
         fclose(f);
     }
     std::mutex mu_;
-    std::map<std::string, int> map_;
+    std::map<std::string, int> chosen_;
+    std::map<std::string, std::map<int, double>> timed_;
     bool loaded_ = false;
 };
 
@@ -665,7 +692,10 @@ public:
         const bool prof = g_profile_on.load() != 0;
         nev_ = 0;
         bool done = false;
-        if (graphs_ && !prof) {
+        bool exploring = false;
+        for (int p = 0; p < 2; ++p)
+            for (const Seg &g : segs_[p]) exploring |= !g.tune_key.empty();
+        if (graphs_ && !prof && !exploring) {
             hipGraphExec_t exec = nullptr;
             auto it = graphs_by_m_.find(m);
             if (it != graphs_by_m_.end()) {
@@ -703,17 +733,37 @@ public:
         ++chunks_;
         HJR_HIP(hipMemcpyAsync(h_states_, d_states_, sizeof(SolveState) * ninst, hipMemcpyDeviceToHost, stream_));
         HJR_HIP(hipStreamSynchronize(stream_));
-        if (prof && nev_ > 0) {
+        if (nev_ > 0) {
+            std::map<std::pair<int, int>, std::vector<float>> tuned;  // (prec, group) -> launch ms
             std::lock_guard<std::mutex> g(g_profile_mu);
             for (int i = 0; i < nev_; ++i) {
                 EvRec &e = evs_[i];
                 float ms = 0.f;
                 HJR_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+                if (e.group >= 0) {
+                    tuned[{e.prec, e.group}].push_back(ms);
+                    continue;
+                }
                 hjr_kernel_time &kt = e.prec ? g_profile.stage64[e.stage] : g_profile.stage32[e.stage];
                 kt.launches += 1;
                 kt.nodes += e.nodes;
                 kt.ms += ms;
             }
+            // the median launch of the chunk (launches after an instance has finished return
+            // at once and would drag a mean down)
+            for (auto &kv : tuned) {
+                auto &v = kv.second;
+                std::sort(v.begin(), v.end());
+                const Seg &sg = segs_[kv.first.first][kv.first.second];
+                if (v.size() >= 3) {
+                    Tuner::get().record(sg.tune_key, sg.npt, 1e3 * v[v.size() / 2]);
+                    if (getenv("HJR_TUNE_VERBOSE"))
+                        fprintf(stderr, "[hjr tune] %s npt=%d launches=%zu min=%.1fus median=%.1fus max=%.1fus\n",
+                                sg.tune_key.c_str(), sg.npt, v.size(), 1e3 * v.front(), 1e3 * v[v.size() / 2],
+                                1e3 * v.back());
+                }
+            }
+            if (!tuned.empty()) dirty_ = true;  // next chunk: next candidate, or the choice
         }
         return HJR_OK;
     }
@@ -827,6 +877,7 @@ private:
         hipEvent_t a, b;
         int prec, stage;
         int64_t nodes;
+        int group;  // >= 0: autotuner timing of segs_[prec][group]; -1: kernel profile
     };
     struct Hist {
         int phase = -1;
@@ -834,7 +885,7 @@ private:
         double delta = 0.0;
     };
 
-    hjr_status event_pair(hipEvent_t *a, hipEvent_t *b, int prec, int stage, int64_t nodes)
+    hjr_status event_pair(hipEvent_t *a, hipEvent_t *b, int prec, int stage, int64_t nodes, int group)
     {
         if (nev_ == (int)evs_.size()) {
             EvRec e{};
@@ -846,6 +897,7 @@ private:
         e.prec = prec;
         e.stage = stage;
         e.nodes = nodes;
+        e.group = group;
         *a = e.a;
         *b = e.b;
         return HJR_OK;
@@ -880,22 +932,22 @@ private:
             for (auto &kv : groups[p]) {
                 const int dyn = kv.first / 8, sp = kv.first % 8;
                 int npt = kFusedNpt;
+                std::string tkey;
                 if (!fused_) {
                     npt = npt_override_;
                     if (!npt) {
                         const std::string k = Tuner::key(p, dyn, sp, kv.second.nodes);
-                        npt = Tuner::get().lookup(k);
+                        npt = Tuner::get().choice(k);
                         if (!npt && autotune_) {
-                            hjr_status s = tune(p, dyn, sp, kv.second.slots, &npt);
-                            if (s != HJR_OK) return s;
-                            Tuner::get().store(k, npt);
+                            npt = Tuner::get().next_candidate(k);
+                            tkey = k;  // this group's launches are timed this chunk
                         }
                         if (!npt) npt = kFusedNpt;
                     }
                 }
                 const int off = (int)t[p].size();
                 append_tiles(kv.second.slots, npt, t[p]);
-                segs_[p].push_back(Seg{dyn, sp, npt, off, (int)t[p].size() - off});
+                segs_[p].push_back(Seg{dyn, sp, npt, off, (int)t[p].size() - off, tkey});
             }
         }
         n32_ = (int)t[0].size();
@@ -943,57 +995,6 @@ private:
         return HJR_OK;
     }
 
-    // Time trial launches of one group for each nodes-per-thread candidate.  The trials write
-    // only buffers the next real step recomputes, and any max-change they accumulate (Euler) is
-    // cleared afterwards.
-    hjr_status tune(int prec, int dyn, int spatial, const std::vector<int> &slots, int *best_npt)
-    {
-        static const int cands[] = {4, 2, 8, 1};  // ties (within 2%) go to the earlier entry
-        float best = 1e30f;
-        *best_npt = kFusedNpt;
-        hipEvent_t a, b;
-        HJR_HIP(hipEventCreate(&a));
-        HJR_HIP(hipEventCreate(&b));
-        for (int npt : cands) {
-            std::vector<Tile> t, none;
-            append_tiles(slots, npt, t);
-            hjr_status s = prec ? upload_tiles(none, t) : upload_tiles(t, none);
-            if (s != HJR_OK) return s;
-            const Tile *dt = prec ? d_tiles64_ : d_tiles32_;
-            const int nt = (int)t.size();
-            // a trial is RK stages 1 and 2, which write only the stage buffers A and B (stage 3
-            // would overwrite the iterate); Euler instances run their single stage into the
-            // ping-pong buffer and skip the second launch
-            auto trial = [&]() -> hipError_t {
-                hipError_t e = launch_stage_one(prec != 0, dyn, spatial, npt, d_insts_, dt, nt, 0, max_blocks_, stream_);
-                if (e == hipSuccess)
-                    e = launch_stage_one(prec != 0, dyn, spatial, npt, d_insts_, dt, nt, 1, max_blocks_, stream_);
-                return e;
-            };
-            HJR_HIP(trial());
-            // best of five: the least disturbed measurement
-            float mine = 1e30f;
-            for (int r = 0; r < 5; ++r) {
-                HJR_HIP(hipEventRecord(a, stream_));
-                HJR_HIP(trial());
-                HJR_HIP(hipEventRecord(b, stream_));
-                HJR_HIP(hipEventSynchronize(b));
-                float ms = 0.f;
-                HJR_HIP(hipEventElapsedTime(&ms, a, b));
-                mine = std::min(mine, ms);
-            }
-            if (mine < 0.98f * best) {
-                best = mine;
-                *best_npt = npt;
-            }
-        }
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
-        HJR_HIP(launch_clear_deltas(d_insts_, top_slot_ + 1, stream_));
-        ++tunings_;
-        return HJR_OK;
-    }
-
     // One stage over every tile of one precision: a single fused launch, or one launch per
     // (model, scheme) group with the kernel specialised to it.
     hjr_status launch_stage_all(int prec, int stage, bool prof)
@@ -1003,7 +1004,7 @@ private:
         const Tile *tl = prec ? d_tiles64_ : d_tiles32_;
         hipEvent_t a = nullptr, b = nullptr;
         if (prof) {
-            hjr_status s = event_pair(&a, &b, prec, stage, nodes_[prec]);
+            hjr_status s = event_pair(&a, &b, prec, stage, nodes_[prec], -1);
             if (s != HJR_OK) return s;
             HJR_HIP(hipEventRecord(a, stream_));
         }
@@ -1011,9 +1012,18 @@ private:
             HJR_HIP(launch_stage(prec != 0, d_insts_, tl, nt, stage, max_blocks_, stream_));
             ++launches_;
         } else {
-            for (const Seg &g : segs_[prec]) {
+            for (int gi = 0; gi < (int)segs_[prec].size(); ++gi) {
+                const Seg &g = segs_[prec][gi];
+                const bool explore = !g.tune_key.empty() && !prof;
+                hipEvent_t ga = nullptr, gb = nullptr;
+                if (explore) {
+                    hjr_status s = event_pair(&ga, &gb, prec, stage, 0, gi);
+                    if (s != HJR_OK) return s;
+                    HJR_HIP(hipEventRecord(ga, stream_));
+                }
                 HJR_HIP(launch_stage_one(prec != 0, g.dyn, g.spatial, g.npt, d_insts_, tl + g.off, g.count, stage,
                                          max_blocks_, stream_));
+                if (explore) HJR_HIP(hipEventRecord(gb, stream_));
                 ++launches_;
             }
         }
@@ -1023,6 +1033,7 @@ private:
 
     struct Seg {
         int dyn, spatial, npt, off, count;
+        std::string tune_key;  // non-empty: this group is being timed for the autotuner
     };
     std::vector<Seg> segs_[2];
     std::map<int, hipGraphExec_t> graphs_by_m_;
@@ -1031,7 +1042,6 @@ private:
     bool fused_ = false;
     bool autotune_ = true;
     int npt_override_ = 0;
-    int tunings_ = 0;
 
     int cap_;
     int device_ = 0;
@@ -1384,7 +1394,7 @@ hjr_status hjr_stage_device(const hjr_grid *grid, const hjr_dynamics *dyn, int32
     int npt = 0;
     if (const char *np = getenv("HJR_NPT")) npt = atoi(np);
     if (npt != 1 && npt != 2 && npt != 4 && npt != 8) npt = 0;
-    if (!npt) npt = Tuner::get().lookup(Tuner::key(f32 ? 0 : 1, dyn->id, spatial, r.npts));
+    if (!npt) npt = Tuner::get().choice(Tuner::key(f32 ? 0 : 1, dyn->id, spatial, r.npts));
     if (!npt || fused) npt = kFusedNpt;
     std::vector<Tile> tiles;
     for (uint64_t s0 = 0; s0 < r.npts; s0 += (uint64_t)npt * kBlock) tiles.push_back(Tile{0, (uint32_t)s0, npt});

@@ -32,7 +32,10 @@ __device__ __forceinline__ unsigned wave_sum(unsigned v)
     return v;
 }
 
-// Block-wide max of a non-negative value, then one atomic max into *dst (FP64 bits).
+// Block-wide max of a non-negative value, then an atomic max into *dst (FP64 bits).  Thousands
+// of workgroups update the same word, so each first reads the word (from L2, relaxed) and
+// issues the atomic only if its value is larger: the word only grows during a launch, so a
+// skipped update was never needed.
 __device__ __forceinline__ void block_max_to(double v, unsigned long long *dst, double *red)
 {
     v = wave_max(v);
@@ -43,7 +46,11 @@ __device__ __forceinline__ void block_max_to(double v, unsigned long long *dst, 
         double m = red[0];
 #pragma unroll
         for (int w = 1; w < kBlock / 64; ++w) m = nanmax(m, red[w]);
-        if (m > 0.0 || m != m) atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(m);
+        if (m > 0.0 || m != m) {
+            const unsigned long long cur = __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (bits > cur) atomicMax(dst, bits);
+        }
     }
     __syncthreads();
 }
@@ -492,19 +499,6 @@ hipError_t launch_stage_one(bool fp64, int dyn, int spatial, int npt, const Inst
         launch_one<double>(dyn, spatial, npt, g, s, insts, tiles, ntiles, stage);
     else
         launch_one<float>(dyn, spatial, npt, g, s, insts, tiles, ntiles, stage);
-    return hipGetLastError();
-}
-
-// Zero the max-change accumulators of every instance (after timing trial launches).
-__global__ void clear_deltas_kernel(const Inst *__restrict__ insts, int ninst)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < ninst) insts[i].state->delta_bits = 0ull;
-}
-
-hipError_t launch_clear_deltas(const Inst *insts, int ninst, hipStream_t s)
-{
-    hipLaunchKernelGGL(clear_deltas_kernel, dim3((ninst + 63) / 64), dim3(64), 0, s, insts, ninst);
     return hipGetLastError();
 }
 

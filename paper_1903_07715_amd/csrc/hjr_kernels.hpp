@@ -9,7 +9,6 @@ hipError_t launch_stage(bool fp64, const Inst *insts, const Tile *tiles, int nti
                         int max_blocks, hipStream_t s);
 hipError_t launch_stage_one(bool fp64, int dyn, int spatial, int npt, const Inst *insts, const Tile *tiles, int ntiles,
                             int stage, int max_blocks, hipStream_t s);
-hipError_t launch_clear_deltas(const Inst *insts, int ninst, hipStream_t s);
 hipError_t launch_step_end(const Inst *insts, int ninst, hipStream_t s);
 hipError_t launch_interval(bool fp64, const Inst *insts, const Tile *tiles, int ntiles, int max_blocks,
                            hipStream_t s);
