@@ -909,6 +909,7 @@ private:
         struct G {
             std::vector<int> slots;
             uint64_t nodes = 0;
+            uint64_t largest = 0;  // size class for the tuner: the group's largest instance
         };
         std::map<int, G> groups[2];
         top_slot_ = -1;
@@ -924,6 +925,7 @@ private:
             G &g = groups[fp64][r->dyn.id * 8 + r->opts.spatial];
             g.slots.push_back(i);
             g.nodes += r->npts;
+            g.largest = std::max(g.largest, r->npts);
         }
         if (top_slot_ < 0) top_slot_ = 0;
         std::vector<Tile> t[2];
@@ -936,7 +938,7 @@ private:
                 if (!fused_) {
                     npt = npt_override_;
                     if (!npt) {
-                        const std::string k = Tuner::key(p, dyn, sp, kv.second.nodes);
+                        const std::string k = Tuner::key(p, dyn, sp, kv.second.largest);
                         npt = Tuner::get().choice(k);
                         if (!npt && autotune_) {
                             npt = Tuner::get().next_candidate(k);
@@ -1443,7 +1445,8 @@ struct hjr_ctx {
     hjr_status fatal = HJR_OK;
     std::string fatal_msg;
     std::thread worker;
-    int steps_per_chunk = 8;
+    ChunkPolicy policy{0};
+    int max_chunk = 32;
 
     void loop()
     {
@@ -1475,9 +1478,11 @@ struct hjr_ctx {
                 }
             }
             if (engine->active() == 0) continue;
-            hjr_status s = engine->run_chunk(steps_per_chunk);
+            // adaptive chunk, capped so that waiting requests join within max_chunk steps
+            hjr_status s = engine->run_chunk(std::min(policy.next(), max_chunk));
             fin.clear();
             if (s == HJR_OK) s = engine->update(fin);
+            if (s == HJR_OK) policy.after(!fin.empty(), engine->predict_steps());
             if (s == HJR_OK && !fin.empty()) {
                 hipError_t e = hipStreamSynchronize(engine->stream());
                 if (e != hipSuccess) s = fail(HJR_ERR_DEVICE, "sync failed: %s", hipGetErrorString(e));
