@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=101, help="grid side (default 101)")
+    ap.add_argument("--polish-shift", type=float, default=-1.0, help="FP64 polish start shift (< 0: automatic)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["dubins", "batch", "serve"], default="dubins",
@@ -141,7 +142,7 @@ def main():
     p = W.dubins_problem(n, dbar=0.1)
     q = W.dubins_problem(n, dbar=0.05)
     npts = p.grid.size
-    opts = hjr.problem_options(p, precision=hjr.FP32_POLISH64, max_iter=20000)
+    opts = hjr.problem_options(p, precision=hjr.FP32_POLISH64, max_iter=20000, polish_shift=args.polish_shift)
     stream = torch.cuda.Stream()
     l_t = torch.tensor(p.l, device=dev)
     lq_t = torch.tensor(q.l, device=dev)
@@ -208,7 +209,7 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
                 "traffic": MEASURED_TRAFFIC.get(kernel_source_hash()),
-                "kernel": "stage_kernel<float> (WENO5 + LF + TVD-RK3 stage, Dubins 3-D)",
+                "kernel": "stage_kernel_one<float, Dubins, WENO5> (WENO5 + LF + TVD-RK3 stage)",
                 "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
                 "algorithmic_gbs": round(BYTES_PER_NODE_STEP_RK3_FP32 / 3 * npts / avg_s / 1e9, 1)}
     line = {
@@ -329,7 +330,7 @@ def bench_serve(args):
             ub, db = rng.uniform(0.5, 2.0), rng.uniform(0.0, 0.2)
             dyn, key = W.double_integrator(ub, 1.0, db), (-ub, db)
             dom = lambda a, b: a[0] <= b[0] and a[1] <= b[1]
-        opts = hjr.problem_options(p, precision=hjr.FP32_POLISH64, max_iter=20000)
+        opts = hjr.problem_options(p, precision=hjr.FP32_POLISH64, max_iter=20000, polish_shift=args.polish_shift)
         return serving.Request(kind=kind, grid=p.grid, dyn=dyn, key=key, dominates=dom, l_dev=l_t, opts=opts,
                                arrival=arrival)
 
