@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -368,6 +369,10 @@ static void build_inst(Request &r, char *base, const Layout &L, std::vector<doub
         const double dx = grid_dx(g, d);
         I.inv_dx64[d] = 1.0 / dx;
         I.inv_dx32[d] = (float)(1.0 / dx);
+        I.hinv_dx64[d] = 0.5 / dx;
+        I.hinv_dx32[d] = (float)(0.5 / dx);
+        I.eps0_64[d] = 4e-18 * dx * dx;
+        I.eps0_32[d] = std::max((float)I.eps0_64[d], FLT_MIN);  // kept normal in FP32
     }
     double c[8];
     make_constants(r.dyn, c);

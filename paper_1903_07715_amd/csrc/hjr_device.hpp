@@ -91,6 +91,10 @@ struct Inst {
     FastDiv div[kMaxDim];
     float inv_dx32[kMaxDim];
     double inv_dx64[kMaxDim];
+    float hinv_dx32[kMaxDim];    // 1 / (2 dx)
+    double hinv_dx64[kMaxDim];
+    float eps0_32[kMaxDim];      // WENO5 epsilon floor for undivided differences: 4e-18 dx^2
+    double eps0_64[kMaxDim];
     float c32[8];        // model constants (see make_constants on the host)
     double c64[8];
     int coord_off[kMaxDim];  // offset of each dim's coordinate table in tab32/tab64
@@ -122,7 +126,8 @@ template <> struct Fields<float> {
     __device__ static float *B(const Inst &I) { return I.B32; }
     __device__ static const float *l(const Inst &I) { return I.l32; }
     __device__ static float *snap(const Inst &I) { return I.Vs32; }
-    __device__ static float inv_dx(const Inst &I, int d) { return I.inv_dx32[d]; }
+    __device__ static float hinv_dx(const Inst &I, int d) { return I.hinv_dx32[d]; }
+    __device__ static float eps0(const Inst &I, int d) { return I.eps0_32[d]; }
     __device__ static float c(const Inst &I, int k) { return I.c32[k]; }
     __device__ static const float *tab(const Inst &I) { return I.tab32; }
 };
@@ -132,13 +137,22 @@ template <> struct Fields<double> {
     __device__ static double *B(const Inst &I) { return I.B64; }
     __device__ static const double *l(const Inst &I) { return I.l64; }
     __device__ static double *snap(const Inst &I) { return I.Vs64; }
-    __device__ static double inv_dx(const Inst &I, int d) { return I.inv_dx64[d]; }
+    __device__ static double hinv_dx(const Inst &I, int d) { return I.hinv_dx64[d]; }
+    __device__ static double eps0(const Inst &I, int d) { return I.eps0_64[d]; }
     __device__ static double c(const Inst &I, int k) { return I.c64[k]; }
     __device__ static const double *tab(const Inst &I) { return I.tab64; }
 };
 
 __device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ inline double recip(double x) { return 1.0 / x; }
+// FP64: the hardware reciprocal estimate refined by two Newton steps r <- r + r(1 - x r), each
+// of which squares the relative error, so the result is within an ulp of 1/x; this replaces
+// the longer scaled IEEE division sequence.  Only used on positive normal arguments.
+__device__ inline double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return fma(fma(-x, r, 1.0), r, r);
+}
 
 // 2^-floor(log2 x) for a positive normal x, from the exponent bits (no division).
 __device__ inline float pow2_recip(float x)
@@ -169,100 +183,125 @@ __device__ __forceinline__ void stg(T *p, uint32_t i, T v)
 }
 
 // ---------------------------------------------------------------------------------------------
-// WENO5 one-sided derivatives at a node from its six first differences d[k] (offset k-2):
-// D- from (d0..d4), D+ from the mirrored (d5..d1) (Jiang-Peng smoothness indicators, ideal
-// weights 0.1/0.6/0.3, eps = 1e-6 max v^2 + 1e-18).  The two share the second differences
-// centred at offsets 0 and 1 and four of the five squares in eps.  The weights
-// a_k = g_k / (S_k + eps)^2 are normalised without forming them: with t_k = (S_k + eps) * 2^-e,
-// e the exponent of eps, t_k lies in [1, 7e7] and a_k / sum a = b_k / sum b for
-// b_k = g_k prod_{j != k} t_j^2, which stays inside the FP32 range and needs one reciprocal.
+// WENO5 one-sided derivatives (Jiang-Peng smoothness indicators, ideal weights 0.1/0.6/0.3,
+// eps = 1e-6 max v^2 + 1e-18 over the five differences v of the stencil) at a node, from its six
+// undivided first differences d[k] = u(k-2) - u(k-3) (offsets k-2): D- from (d0..d4), D+ from
+// the mirrored (d5..d1).  Both come out multiplied by dx.
+// The weights depend only on the ratios of the (S_k + eps), so every S_k and eps may carry one
+// common factor: with undivided differences and a factor 4 the indicators are
+// S_k = (13/3) c_k^2 + r_k^2 and eps = 4e-6 max d^2 + 4e-18 dx^2 (eps0).  The two derivatives
+// share the second differences c centred at offsets -1, 0, 1, 2 and four of the five squares in
+// eps.  With a_k = g_k / (S_k + eps)^2, the normalised combination sum a_k phi_k / sum a_k is
+// formed without the a_k: t_k = (S_k + eps) 2^-e (e the exponent of eps) lies in [1, 7e7], and
+// a_k is proportional to g_k prod_{j != k} t_j^2, which stays inside the FP32 range; the ideal
+// weights are folded in as 0.1 : 0.6 : 0.3 = 1 : 6 : 3, with 6 phi_2 and 3 phi_3 formed
+// directly, so one reciprocal finishes the derivative.
 // ---------------------------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ T weno5_combine(T S1, T S2, T S3, T eps, T phi1, T phi2, T phi3)
+__device__ __forceinline__ T weno5_combine(T S1, T S2, T S3, T eps, T f1, T f6, T f3)
 {
     const T sc = pow2_recip(eps);
     const T e = eps * sc;
     const T t1 = S1 * sc + e, t2 = S2 * sc + e, t3 = S3 * sc + e;
     const T s1 = t1 * t1, s2 = t2 * t2, s3 = t3 * t3;
-    const T b1 = T(0.1) * (s2 * s3);
-    const T b2 = T(0.6) * (s1 * s3);
-    const T b3 = T(0.3) * (s1 * s2);
-    return (b1 * phi1 + b2 * phi2 + b3 * phi3) * recip(b1 + b2 + b3);
+    const T p23 = s2 * s3, p13 = s1 * s3, p12 = s1 * s2;
+    return (p23 * f1 + p13 * f6 + p12 * f3) * recip(p23 + T(6) * p13 + T(3) * p12);
 }
 
 template <typename T>
-__device__ __forceinline__ void weno5_pair(const T *d, T &dm, T &dp)
+__device__ __forceinline__ void weno5_pair(const T *d, T eps0, T &dm, T &dp)
 {
-    const T k13 = T(13.0 / 12.0);
-    // second differences centred at offsets -1, 0, 1, 2
+    const T k = T(13.0 / 3.0);
     const T c1 = d[0] - T(2) * d[1] + d[2];
     const T c2 = d[1] - T(2) * d[2] + d[3];
     const T c3 = d[2] - T(2) * d[3] + d[4];
     const T c4 = d[3] - T(2) * d[4] + d[5];
-    const T q1 = k13 * c1 * c1, q2 = k13 * c2 * c2, q3 = k13 * c3 * c3, q4 = k13 * c4 * c4;
+    const T q1 = (k * c1) * c1, q2 = (k * c2) * c2, q3 = (k * c3) * c3, q4 = (k * c4) * c4;
     const T mid = fmax(fmax(d[1] * d[1], d[2] * d[2]), fmax(d[3] * d[3], d[4] * d[4]));
-    // D-: v = (d0, d1, d2, d3, d4)
+    // D-: v = (d0, d1, d2, d3, d4); phi_1, 6 phi_2, 3 phi_3 of the three candidate stencils
     {
         const T r1 = d[0] - T(4) * d[1] + T(3) * d[2];
         const T r2 = d[1] - d[3];
         const T r3 = T(3) * d[2] - T(4) * d[3] + d[4];
-        const T S1 = q1 + T(0.25) * r1 * r1, S2 = q2 + T(0.25) * r2 * r2, S3 = q3 + T(0.25) * r3 * r3;
-        const T eps = T(1e-6) * fmax(mid, d[0] * d[0]) + T(1e-18);
-        const T phi1 = d[0] * T(1.0 / 3.0) - d[1] * T(7.0 / 6.0) + d[2] * T(11.0 / 6.0);
-        const T phi2 = -d[1] * T(1.0 / 6.0) + d[2] * T(5.0 / 6.0) + d[3] * T(1.0 / 3.0);
-        const T phi3 = d[2] * T(1.0 / 3.0) + d[3] * T(5.0 / 6.0) - d[4] * T(1.0 / 6.0);
-        dm = weno5_combine(S1, S2, S3, eps, phi1, phi2, phi3);
+        const T S1 = r1 * r1 + q1, S2 = r2 * r2 + q2, S3 = r3 * r3 + q3;
+        const T eps = T(4e-6) * fmax(mid, d[0] * d[0]) + eps0;
+        const T f1 = d[0] * T(1.0 / 3.0) - d[1] * T(7.0 / 6.0) + d[2] * T(11.0 / 6.0);
+        const T f6 = T(5) * d[2] - d[1] + T(2) * d[3];
+        const T f3 = d[2] + T(2.5) * d[3] - T(0.5) * d[4];
+        dm = weno5_combine(S1, S2, S3, eps, f1, f6, f3);
     }
     // D+: v = (d5, d4, d3, d2, d1)
     {
         const T r1 = d[5] - T(4) * d[4] + T(3) * d[3];
         const T r2 = d[4] - d[2];
         const T r3 = T(3) * d[3] - T(4) * d[2] + d[1];
-        const T S1 = q4 + T(0.25) * r1 * r1, S2 = q3 + T(0.25) * r2 * r2, S3 = q2 + T(0.25) * r3 * r3;
-        const T eps = T(1e-6) * fmax(mid, d[5] * d[5]) + T(1e-18);
-        const T phi1 = d[5] * T(1.0 / 3.0) - d[4] * T(7.0 / 6.0) + d[3] * T(11.0 / 6.0);
-        const T phi2 = -d[4] * T(1.0 / 6.0) + d[3] * T(5.0 / 6.0) + d[2] * T(1.0 / 3.0);
-        const T phi3 = d[3] * T(1.0 / 3.0) + d[2] * T(5.0 / 6.0) - d[1] * T(1.0 / 6.0);
-        dp = weno5_combine(S1, S2, S3, eps, phi1, phi2, phi3);
+        const T S1 = r1 * r1 + q4, S2 = r2 * r2 + q3, S3 = r3 * r3 + q2;
+        const T eps = T(4e-6) * fmax(mid, d[5] * d[5]) + eps0;
+        const T f1 = d[5] * T(1.0 / 3.0) - d[4] * T(7.0 / 6.0) + d[3] * T(11.0 / 6.0);
+        const T f6 = T(5) * d[3] - d[4] + T(2) * d[2];
+        const T f3 = d[3] + T(2.5) * d[2] - T(0.5) * d[1];
+        dp = weno5_combine(S1, S2, S3, eps, f1, f6, f3);
     }
+}
+
+// Every lane of a block works on one tile of one instance, so the instance's array pointers are
+// wave-uniform.  Saying so (readfirstlane of both halves) puts them in scalar registers, and
+// each stencil load then becomes a scalar base plus one shared per-lane byte offset instead of
+// a per-lane 64-bit address computation.
+template <typename P>
+__device__ __forceinline__ P *uniform_ptr(P *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (P *)(((uint64_t)hi << 32) | lo);
 }
 
 // Stencil values along one dim: u[o + H] = S at line position j + o, o = -H..H (H = 3 for WENO5,
-// 1 for upwind), wrapped on a periodic dim and clamped to the line on a non-periodic one (the
-// clamped values are replaced by extrapolated differences in line_derivs).  The centre value is
-// shared by every dim and is not loaded here.
+// 1 for upwind); the centre value is shared by every dim and is not loaded here.
+// inner: every lane of the wave has j in [H, n - H), so no offset leaves the line and the loads
+// use the wave-uniform base S + o * stride.  Otherwise, per lane: on a periodic dim an offset
+// past an end wraps once (n >= 2H + 1, so one wrap is enough); on a non-periodic dim a position
+// off the line loads the centre instead, because line_derivs replaces every difference that
+// involves such a position (any finite in-line value will do).
 template <typename T, int SPATIAL>
 __device__ __forceinline__ void line_load(const T *__restrict__ S, uint32_t node, int j, int n, uint32_t stride,
-                                          bool periodic, T *u)
+                                          bool periodic, bool inner, T *u)
 {
     constexpr int H = SPATIAL == kWeno5 ? 3 : 1;
+    if (inner) {
+#pragma unroll
+        for (int o = -H; o <= H; ++o)
+            if (o != 0) u[o + H] = ldg(S + o * (int)stride, node);
+        return;
+    }
 #pragma unroll
     for (int o = -H; o <= H; ++o) {
         if (o == 0) continue;
-        int jj = j + o;
-        if (periodic) {
-            jj += jj < 0 ? n : 0;
-            jj -= jj >= n ? n : 0;
-        } else {
-            jj = jj < 0 ? 0 : (jj > n - 1 ? n - 1 : jj);
-        }
-        u[o + H] = ldg(S, node + (uint32_t)((jj - j) * (int)stride));
+        int off;
+        if (periodic)
+            off = o < 0 ? (j + o < 0 ? o + n : o) : (j + o >= n ? o - n : o);
+        else
+            off = (o < 0 ? j + o >= 0 : j + o < n) ? o : 0;
+        u[o + H] = ldg(S, node + (uint32_t)(off * (int)stride));
     }
 }
 
-// Left and right derivatives D-V, D+V at node j of a line of n nodes from its stencil values.
-// First differences r[k] = (u[k+1] - u[k]) / dx (WENO5: offsets -2..3; upwind: 0..1).  On a
+// Left and right derivatives D-V, D+V at node j of a line of n nodes from its stencil values,
+// both multiplied by dx.  Undivided first differences r[k] = u[k+1] - u[k] (WENO5: offsets
+// -2..3; upwind: 0..1).  On a
 // non-periodic dim a difference beyond an edge equals the nearest interior one (linear
-// extrapolation of V); waves whose nodes are all at least H nodes from both ends skip that rule
-// (the vote is per wave, so the branch never diverges).
+// extrapolation of V); waves whose nodes are all at least H nodes from both ends (inner, a
+// per-wave vote, so the branch never diverges) skip that rule.
 template <typename T, int SPATIAL>
-__device__ __forceinline__ void line_derivs(const T *u, int j, int n, bool periodic, T inv_dx, T &dm, T &dp)
+__device__ __forceinline__ void line_derivs(const T *u, int j, int n, bool periodic, bool inner, T eps0, T &dm,
+                                            T &dp)
 {
     constexpr int H = SPATIAL == kWeno5 ? 3 : 1;
     T r[2 * H];
 #pragma unroll
     for (int o = -H + 1; o <= H; ++o) r[o + H - 1] = u[o + H] - u[o + H - 1];
-    if (!periodic && !__all(j >= H && j < n - H)) {
+    if (!periodic && !inner) {
         const int lo = 1 - j, hi = n - 1 - j;  // offsets of the first and last valid difference
         T rlo = r[0], rhi = r[2 * H - 1];
 #pragma unroll
@@ -278,10 +317,8 @@ __device__ __forceinline__ void line_derivs(const T *u, int j, int n, bool perio
             r[o + H - 1] = v;
         }
     }
-#pragma unroll
-    for (int k = 0; k < 2 * H; ++k) r[k] *= inv_dx;
     if constexpr (SPATIAL == kWeno5) {
-        weno5_pair<T>(r, dm, dp);
+        weno5_pair<T>(r, eps0, dm, dp);
     } else {
         dm = r[0];
         dp = r[1];
@@ -376,25 +413,31 @@ __device__ __forceinline__ T lf_operator(const Inst &I, const T *__restrict__ S,
     constexpr int N = DynDim<DYN>::value;
     constexpr int W = SPATIAL == kWeno5 ? 7 : 3;
     using F = Fields<T>;
+    constexpr int H = W / 2;
     int idx[N];
+    bool inner[N];
     unflatten<N>(I, node, idx);
     T u[N][W];
     const T c = ldg(S, node);
 #pragma unroll
     for (int d = 0; d < N; ++d) {
-        line_load<T, SPATIAL>(S, node, idx[d], I.n[d], I.stride[d], (I.periodic >> d) & 1u, u[d]);
-        u[d][W / 2] = c;
+        // the last dim is the contiguous one (stride 1 is then a compile-time constant)
+        const uint32_t stride = d == N - 1 ? 1u : I.stride[d];
+        inner[d] = __all(idx[d] >= H && idx[d] < I.n[d] - H);
+        line_load<T, SPATIAL>(S, node, idx[d], I.n[d], stride, (I.periodic >> d) & 1u, inner[d], u[d]);
+        u[d][H] = c;
     }
     T p[N], diff[N], alpha[N];
 #pragma unroll
     for (int d = 0; d < N; ++d) {
         T dm, dp;
-        line_derivs<T, SPATIAL>(u[d], idx[d], I.n[d], (I.periodic >> d) & 1u, F::inv_dx(I, d), dm, dp);
-        p[d] = T(0.5) * (dm + dp);
-        diff[d] = T(0.5) * (dp - dm);
+        line_derivs<T, SPATIAL>(u[d], idx[d], I.n[d], (I.periodic >> d) & 1u, inner[d], F::eps0(I, d), dm, dp);
+        const T h = F::hinv_dx(I, d);
+        p[d] = h * (dm + dp);
+        diff[d] = h * (dp - dm);
     }
     const T sgn = I.game == 0 ? T(1) : T(-1);
-    T L = hamiltonian<T, DYN>(I, F::tab(I), idx, p, alpha, sgn);
+    T L = hamiltonian<T, DYN>(I, uniform_ptr(F::tab(I)), idx, p, alpha, sgn);
 #pragma unroll
     for (int d = 0; d < N; ++d) L += alpha[d] * diff[d];
     *centre = c;

@@ -106,7 +106,10 @@ __device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int st
         S = B; Vn = V; O = V;
     }
     const bool last = euler || stage == 2;
-    const T *l = F::l(I);
+    S = uniform_ptr(S);
+    Vn = uniform_ptr(Vn);
+    O = uniform_ptr(O);
+    const T *l = uniform_ptr(F::l(I));
     double delta = 0.0;
     // NPT nodes per thread, kBlock apart: independent work the scheduler can interleave
     auto one = [&](uint32_t node) {
