@@ -260,7 +260,7 @@ __device__ __forceinline__ P *uniform_ptr(P *p)
 // Stencil values along one dim: u[o + H] = S at line position j + o, o = -H..H (H = 3 for WENO5,
 // 1 for upwind); the centre value is shared by every dim and is not loaded here.
 // inner: every lane of the wave has j in [H, n - H), so no offset leaves the line and the loads
-// use the wave-uniform base S + o * stride.  Otherwise, per lane: on a periodic dim an offset
+// use the wave-uniform offsets o * stride.  Otherwise, per lane: on a periodic dim an offset
 // past an end wraps once (n >= 2H + 1, so one wrap is enough); on a non-periodic dim a position
 // off the line loads the centre instead, because line_derivs replaces every difference that
 // involves such a position (any finite in-line value will do).
@@ -272,7 +272,7 @@ __device__ __forceinline__ void line_load(const T *__restrict__ S, uint32_t node
     if (inner) {
 #pragma unroll
         for (int o = -H; o <= H; ++o)
-            if (o != 0) u[o + H] = ldg(S + o * (int)stride, node);
+            if (o != 0) u[o + H] = ldg(S, node + (uint32_t)(o * (int)stride));
         return;
     }
 #pragma unroll
