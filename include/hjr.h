@@ -206,10 +206,12 @@ hjr_status hjr_stage_device(const hjr_grid *grid, const hjr_dynamics *dyn, int32
                             double dt, const void *Vs, const void *Vn, const void *l, void *out,
                             double *delta_out, void *stream);
 
-/* Kernel timing: while enabled (process-wide), the solvers bracket every stage-kernel launch
- * with HIP events on the stream it runs on and accumulate the elapsed times; hjr_profile_read
- * returns the totals since the last reset.  `nodes` counts grid nodes covered by the launches'
- * tile lists (including nodes of instances that had already finished). */
+/* Kernel timing: while enabled (process-wide), the solvers launch every stage kernel with a
+ * pair of HIP events that the launch itself stamps with the kernel's start and end (so gaps in
+ * the stream are not counted) and accumulate the durations; hjr_profile_read returns the totals
+ * since the last reset.  `launches` counts kernel launches (one per model/scheme group and
+ * stage); `nodes` counts grid nodes covered by their tile lists (including nodes of instances
+ * that had already finished). */
 typedef struct {
     int64_t launches;
     int64_t nodes;

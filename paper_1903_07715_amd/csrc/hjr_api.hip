@@ -954,7 +954,7 @@ private:
                 }
                 const int off = (int)t[p].size();
                 append_tiles(kv.second.slots, npt, t[p]);
-                segs_[p].push_back(Seg{dyn, sp, npt, off, (int)t[p].size() - off, tkey});
+                segs_[p].push_back(Seg{dyn, sp, npt, off, (int)t[p].size() - off, (int64_t)kv.second.nodes, tkey});
             }
         }
         n32_ = (int)t[0].size();
@@ -1009,37 +1009,38 @@ private:
         const int nt = prec ? n64_ : n32_;
         if (nt <= 0) return HJR_OK;
         const Tile *tl = prec ? d_tiles64_ : d_tiles32_;
-        hipEvent_t a = nullptr, b = nullptr;
-        if (prof) {
-            hjr_status s = event_pair(&a, &b, prec, stage, nodes_[prec], -1);
-            if (s != HJR_OK) return s;
-            HJR_HIP(hipEventRecord(a, stream_));
-        }
         if (fused_) {
-            HJR_HIP(launch_stage(prec != 0, d_insts_, tl, nt, stage, max_blocks_, stream_));
-            ++launches_;
-        } else {
-            for (int gi = 0; gi < (int)segs_[prec].size(); ++gi) {
-                const Seg &g = segs_[prec][gi];
-                const bool explore = !g.tune_key.empty() && !prof;
-                hipEvent_t ga = nullptr, gb = nullptr;
-                if (explore) {
-                    hjr_status s = event_pair(&ga, &gb, prec, stage, 0, gi);
-                    if (s != HJR_OK) return s;
-                    HJR_HIP(hipEventRecord(ga, stream_));
-                }
-                HJR_HIP(launch_stage_one(prec != 0, g.dyn, g.spatial, g.npt, d_insts_, tl + g.off, g.count, stage,
-                                         max_blocks_, stream_));
-                if (explore) HJR_HIP(hipEventRecord(gb, stream_));
-                ++launches_;
+            hipEvent_t a = nullptr, b = nullptr;
+            if (prof) {
+                hjr_status s = event_pair(&a, &b, prec, stage, nodes_[prec], -1);
+                if (s != HJR_OK) return s;
+                HJR_HIP(hipEventRecord(a, stream_));
             }
+            HJR_HIP(launch_stage(prec != 0, d_insts_, tl, nt, stage, max_blocks_, stream_));
+            if (prof) HJR_HIP(hipEventRecord(b, stream_));
+            ++launches_;
+            return HJR_OK;
         }
-        if (prof) HJR_HIP(hipEventRecord(b, stream_));
+        // per-group kernel durations (profile, or the autotuner's timing of a candidate) come
+        // from events stamped by the launch itself with the kernel's start and end
+        for (int gi = 0; gi < (int)segs_[prec].size(); ++gi) {
+            const Seg &g = segs_[prec][gi];
+            const bool explore = !g.tune_key.empty() && !prof;
+            hipEvent_t ga = nullptr, gb = nullptr;
+            if (prof || explore) {
+                hjr_status s = event_pair(&ga, &gb, prec, stage, prof ? g.nodes : 0, prof ? -1 : gi);
+                if (s != HJR_OK) return s;
+            }
+            HJR_HIP(launch_stage_one(prec != 0, g.dyn, g.spatial, g.npt, d_insts_, tl + g.off, g.count, stage,
+                                     max_blocks_, stream_, ga, gb));
+            ++launches_;
+        }
         return HJR_OK;
     }
 
     struct Seg {
         int dyn, spatial, npt, off, count;
+        int64_t nodes;         // nodes of the group's instances
         std::string tune_key;  // non-empty: this group is being timed for the autotuner
     };
     std::vector<Seg> segs_[2];

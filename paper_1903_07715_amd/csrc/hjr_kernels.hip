@@ -7,6 +7,8 @@
 // the eight XCDs round-robin) takes one contiguous run of tiles: the stencil halo of a tile is
 // then mostly in the same XCD's L2.  A grid smaller than the tile count makes each workgroup
 // loop over its XCD's run (persistent mode).
+#include <hip/hip_ext.h>
+
 #include "hjr_kernels.hpp"
 
 namespace hjr {
@@ -460,12 +462,21 @@ hipError_t launch_stage(bool fp64, const Inst *insts, const Tile *tiles, int nti
     return hipGetLastError();
 }
 
+// With ev0/ev1 the launch goes through hipExtLaunchKernel, which stamps the two events with the
+// kernel's own start and end (so their interval is the kernel's duration, without queue gaps).
 template <typename T, int NPT>
 static void launch_one_npt(int dyn, int spatial, dim3 g, hipStream_t s, const Inst *insts, const Tile *tiles,
-                           int ntiles, int stage)
+                           int ntiles, int stage, hipEvent_t ev0, hipEvent_t ev1)
 {
-#define HJR_ONE(D, SP)                                                                                   \
-    hipLaunchKernelGGL((stage_kernel_one<T, D, SP, NPT>), g, dim3(kBlock), 0, s, insts, tiles, ntiles, stage)
+#define HJR_ONE(D, SP)                                                                                         \
+    do {                                                                                                       \
+        if (ev0 || ev1)                                                                                        \
+            hipExtLaunchKernelGGL((stage_kernel_one<T, D, SP, NPT>), g, dim3(kBlock), 0, s, ev0, ev1, 0u, insts, \
+                                  tiles, ntiles, stage);                                                       \
+        else                                                                                                   \
+            hipLaunchKernelGGL((stage_kernel_one<T, D, SP, NPT>), g, dim3(kBlock), 0, s, insts, tiles, ntiles,   \
+                               stage);                                                                         \
+    } while (0)
     const int key = dyn * 8 + spatial;
     switch (key) {
     case kDynDI * 8 + kUpwind1: HJR_ONE(kDynDI, kUpwind1); break;
@@ -483,25 +494,25 @@ static void launch_one_npt(int dyn, int spatial, dim3 g, hipStream_t s, const In
 
 template <typename T>
 static void launch_one(int dyn, int spatial, int npt, dim3 g, hipStream_t s, const Inst *insts, const Tile *tiles,
-                       int ntiles, int stage)
+                       int ntiles, int stage, hipEvent_t ev0, hipEvent_t ev1)
 {
     switch (npt) {
-    case 1: launch_one_npt<T, 1>(dyn, spatial, g, s, insts, tiles, ntiles, stage); break;
-    case 2: launch_one_npt<T, 2>(dyn, spatial, g, s, insts, tiles, ntiles, stage); break;
-    case 8: launch_one_npt<T, 8>(dyn, spatial, g, s, insts, tiles, ntiles, stage); break;
-    default: launch_one_npt<T, 4>(dyn, spatial, g, s, insts, tiles, ntiles, stage); break;
+    case 1: launch_one_npt<T, 1>(dyn, spatial, g, s, insts, tiles, ntiles, stage, ev0, ev1); break;
+    case 2: launch_one_npt<T, 2>(dyn, spatial, g, s, insts, tiles, ntiles, stage, ev0, ev1); break;
+    case 8: launch_one_npt<T, 8>(dyn, spatial, g, s, insts, tiles, ntiles, stage, ev0, ev1); break;
+    default: launch_one_npt<T, 4>(dyn, spatial, g, s, insts, tiles, ntiles, stage, ev0, ev1); break;
     }
 }
 
 hipError_t launch_stage_one(bool fp64, int dyn, int spatial, int npt, const Inst *insts, const Tile *tiles, int ntiles,
-                            int stage, int max_blocks, hipStream_t s)
+                            int stage, int max_blocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (ntiles <= 0) return hipSuccess;
     const dim3 g(grid_for(ntiles, max_blocks));
     if (fp64)
-        launch_one<double>(dyn, spatial, npt, g, s, insts, tiles, ntiles, stage);
+        launch_one<double>(dyn, spatial, npt, g, s, insts, tiles, ntiles, stage, ev0, ev1);
     else
-        launch_one<float>(dyn, spatial, npt, g, s, insts, tiles, ntiles, stage);
+        launch_one<float>(dyn, spatial, npt, g, s, insts, tiles, ntiles, stage, ev0, ev1);
     return hipGetLastError();
 }
 
