@@ -88,6 +88,12 @@ def _load():
         lib.or_step.argtypes = [P(_Grid), P(_Dyn), P(_Opts), dp, dp, C.c_double, dp, dp]
         lib.or_solve.argtypes = [P(_Grid), P(_Dyn), dp, dp, P(_Opts), dp, P(_Result)]
         lib.or_threads.restype = C.c_int
+        lib.or_num_controls.argtypes = [C.c_int]
+        lib.or_num_controls.restype = C.c_int
+        lib.or_gradient_at.argtypes = [P(_Grid), C.c_int, dp, C.c_int64, dp]
+        lib.or_interp_at.argtypes = [P(_Grid), C.c_int, dp, dp, dp, dp]
+        lib.or_optimal_control.argtypes = [P(_Dyn), C.c_int, dp, dp, dp]
+        lib.or_safe_control.argtypes = [P(_Grid), P(_Dyn), C.c_int, C.c_int, dp, dp, C.c_int64, dp, dp, dp]
         _lib = lib
     return _lib
 
@@ -243,3 +249,49 @@ def problem_opts(problem) -> dict:
     """Scheme options of a workloads.Problem."""
     return dict(spatial=problem.spatial, temporal=problem.temporal, game=problem.game, cfl=problem.cfl,
                 tol=problem.tol)
+
+
+def num_controls(dyn) -> int:
+    return int(_load().or_num_controls(dyn.id))
+
+
+def gradient_at(grid, V, nodes, spatial=UPWIND1) -> np.ndarray:
+    """Nodal gradient (D- + D+)/2 at the given flat nodes: array (len(nodes), ndim)."""
+    V = _f64(V)
+    if V.size != grid.size:
+        raise ValueError("V does not match the grid")
+    nodes = np.asarray(nodes, dtype=np.int64).ravel()
+    out = np.empty((nodes.shape[0], grid.ndim))
+    g = _grid(grid)
+    lib = _load()
+    for i, nd in enumerate(nodes):
+        row = np.empty(grid.ndim)
+        if lib.or_gradient_at(C.byref(g), spatial, _ptr(V), int(nd), _ptr(row)):
+            raise ValueError("or_gradient_at failed")
+        out[i] = row
+    return out
+
+
+def optimal_control(dyn, x, p, game=AVOID) -> np.ndarray:
+    u = np.zeros(3)
+    if _load().or_optimal_control(C.byref(_dyn(dyn)), game, _ptr(_f64(x)), _ptr(_f64(p)), _ptr(u)):
+        raise ValueError("or_optimal_control failed")
+    return u[: num_controls(dyn)].copy()
+
+
+def safe_control(grid, dyn, V, x, game=AVOID, spatial=UPWIND1):
+    """Safe control at states x (nq x ndim): returns (u (nq x nu), p (nq x ndim), v (nq))."""
+    V = _f64(V)
+    if V.size != grid.size:
+        raise ValueError("V does not match the grid")
+    x = _f64(x).reshape(-1, grid.ndim)
+    nq = x.shape[0]
+    nu = num_controls(dyn)
+    u = np.empty((nq, nu))
+    p = np.empty((nq, grid.ndim))
+    v = np.empty(nq)
+    rc = _load().or_safe_control(C.byref(_grid(grid)), C.byref(_dyn(dyn)), game, spatial, _ptr(V), _ptr(x), nq,
+                                 _ptr(u), _ptr(p), _ptr(v))
+    if rc:
+        raise ValueError("or_safe_control failed")
+    return u, p, v

@@ -646,3 +646,166 @@ int or_solve(const or_grid *g, const or_dyn *dyn, const double *l, const double 
     free(Vstart);
     return 0;
 }
+
+/* ------------------------------------------------------------------------------------------ */
+/* Safe control (Sec. II-B.2, eq. (uOpt)): at a state x, with p the gradient of the converged   */
+/* value function there, the safe controller applies u* = argmax_u min_d <p, f(x, u, d)> (avoid */
+/* game; argmin_u max_d for the reach game).                                                   */
+/* ------------------------------------------------------------------------------------------ */
+
+int or_num_controls(int id)
+{
+    switch (id) {
+    case 1: return 1;
+    case 2: return 1;
+    case 3: return 2;
+    case 4: return 3;
+    default: return -1;
+    }
+}
+
+/* Gradient at a grid node: the average (D- + D+)/2 of the solver's one-sided derivatives (the
+ * same p the Hamiltonian is evaluated at in the Lax-Friedrichs operator). */
+int or_gradient_at(const or_grid *g, int spatial, const double *V, int64_t node, double *p)
+{
+    for (int d = 0; d < g->ndim; ++d) {
+        double dm, dp;
+        if (or_derivatives(g, spatial, V, node, d, &dm, &dp) != 0) return -1;
+        p[d] = 0.5 * (dm + dp);
+    }
+    return 0;
+}
+
+/* The grid cell holding coordinate x along dim d: lower node j, upper node jn and the weight w
+ * of the upper node (linear interpolation).  Non-periodic dims clamp x into [lo, hi]; periodic
+ * dims reduce it into one period. */
+static void cell_of(const or_grid *g, int d, double x, int *j, int *jn, double *w)
+{
+    int n = g->n[d];
+    double s = (x - g->lo[d]) / grid_dx(g, d);
+    if (is_periodic(g, d)) {
+        s = s - (double)n * floor(s / (double)n);
+        int k = (int)floor(s);
+        if (k > n - 1) k = n - 1;
+        if (k < 0) k = 0;
+        *j = k;
+        *jn = k + 1 == n ? 0 : k + 1;
+        *w = s - (double)k;
+    } else {
+        if (s < 0.0) s = 0.0;
+        if (s > (double)(n - 1)) s = (double)(n - 1);
+        int k = (int)floor(s);
+        if (k > n - 2) k = n - 2;
+        *j = k;
+        *jn = k + 1;
+        *w = s - (double)k;
+    }
+}
+
+/* Multilinear interpolation at x of the nodal gradient (p, ndim values) and of V (*v), over
+ * the 2^ndim corners of x's cell; corner c takes the upper node along dim d when bit d of c is
+ * set, with weight prod_d (bit ? w_d : 1 - w_d). */
+int or_interp_at(const or_grid *g, int spatial, const double *V, const double *x, double *p,
+                 double *v)
+{
+    if (!grid_ok(g)) return -1;
+    int nd = g->ndim;
+    int j[OR_MAXD], jn[OR_MAXD];
+    double w[OR_MAXD];
+    for (int d = 0; d < nd; ++d) cell_of(g, d, x[d], &j[d], &jn[d], &w[d]);
+    for (int d = 0; d < nd; ++d) p[d] = 0.0;
+    double acc = 0.0;
+    for (int c = 0; c < (1 << nd); ++c) {
+        double wt = 1.0;
+        int64_t node = 0;
+        for (int d = 0; d < nd; ++d) {
+            int up = (c >> d) & 1;
+            wt *= up ? w[d] : 1.0 - w[d];
+            node += (int64_t)(up ? jn[d] : j[d]) * grid_stride(g, d);
+        }
+        double pc[OR_MAXD];
+        if (or_gradient_at(g, spatial, V, node, pc) != 0) return -1;
+        for (int d = 0; d < nd; ++d) p[d] += wt * pc[d];
+        acc += wt * V[node];
+    }
+    if (v) *v = acc;
+    return 0;
+}
+
+/* min over the disturbance set (avoid) or max (reach) of <p, f(x, u, d)> for one control u. */
+static double inner_value(const or_dyn *dyn, int game, const double *x, const double *p,
+                          const double *u)
+{
+    int nd = dyn_ndim(dyn->id);
+    double f[OR_MAXD];
+    double zero[3] = {0.0, 0.0, 0.0};
+    if (ball_disturbance(dyn)) {
+        or_flow(dyn, x, u, zero, f);
+        double s = 0.0;
+        for (int i = 0; i < nd; ++i) s += p[i] * f[i];
+        double pn = sqrt(p[0] * p[0] + p[1] * p[1]);
+        return game == OR_AVOID ? s - dyn->p[2] * pn : s + dyn->p[2] * pn;
+    }
+    double D[8][3];
+    memset(D, 0, sizeof D);
+    int ndist = disturbance_corners(dyn, D);
+    double best = game == OR_AVOID ? INFINITY : -INFINITY;
+    for (int b = 0; b < ndist; ++b) {
+        or_flow(dyn, x, u, D[b], f);
+        double s = 0.0;
+        for (int i = 0; i < nd; ++i) s += p[i] * f[i];
+        if (game == OR_AVOID) best = s < best ? s : best;
+        else best = s > best ? s : best;
+    }
+    return best;
+}
+
+/* u* at state x for gradient p: the corner of the control box that maximises (avoid) or
+ * minimises (reach) the inner value; the objective is affine (or monotone) in each control, so
+ * a corner attains the optimum.  Corners are visited in the order of control_corners and a
+ * later corner that ties the best so far replaces it, so a control whose coefficient in the
+ * objective is zero ends at its upper bound. */
+int or_optimal_control(const or_dyn *dyn, int game, const double *x, const double *p, double *u)
+{
+    int nu = or_num_controls(dyn->id);
+    if (nu < 0) return -1;
+    double U[8][3];
+    memset(U, 0, sizeof U);
+    int nc = control_corners(dyn, U);
+    int best_c = -1;
+    double best = 0.0;
+    for (int c = 0; c < nc; ++c) {
+        double val = inner_value(dyn, game, x, p, U[c]);
+        if (best_c < 0 || (game == OR_AVOID ? val >= best : val <= best)) {
+            best = val;
+            best_c = c;
+        }
+    }
+    for (int i = 0; i < nu; ++i) u[i] = U[best_c][i];
+    return 0;
+}
+
+/* The whole query: for each of the nq states x (row-major, nq x ndim) the interpolated
+ * gradient p (nq x ndim), value v (nq) and safe control u (nq x nu).  p and v may be NULL. */
+int or_safe_control(const or_grid *g, const or_dyn *dyn, int game, int spatial, const double *V,
+                    const double *x, int64_t nq, double *u, double *p, double *v)
+{
+    int nd = dyn_ndim(dyn->id);
+    int nu = or_num_controls(dyn->id);
+    if (!grid_ok(g) || nd != g->ndim || nu < 0 || nq < 0) return -1;
+    if (spatial != OR_UPWIND1 && spatial != OR_WENO5) return -1;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t q = 0; q < nq; ++q) {
+        double pq[OR_MAXD], vq;
+        if (or_interp_at(g, spatial, V, x + q * nd, pq, &vq) != 0) {
+            bad = 1;
+            continue;
+        }
+        if (or_optimal_control(dyn, game, x + q * nd, pq, u + q * nu) != 0) bad = 1;
+        if (p)
+            for (int d = 0; d < nd; ++d) p[q * nd + d] = pq[d];
+        if (v) v[q] = vq;
+    }
+    return bad ? -1 : 0;
+}

@@ -99,4 +99,19 @@ int or_solve(const or_grid *g, const or_dyn *dyn, const double *l, const double 
              const or_opts *o, double *V, or_result *res);
 int or_threads(void);
 
+/* Safe control (Sec. II-B.2, eq. (uOpt)).  or_num_controls: number of control inputs of a model
+ * (1, 1, 2, 3 for ids 1-4; -1 otherwise).  or_gradient_at: p = (D- + D+)/2 at a node.
+ * or_interp_at: p and V at a state x by multilinear interpolation of the nodal values over x's
+ * cell (non-periodic coordinates clamped into [lo, hi], periodic ones wrapped).
+ * or_optimal_control: u* = argmax_u min_d <p, f> (avoid) / argmin_u max_d (reach) by
+ * enumerating the corners of the control box; on ties the later corner wins.
+ * or_safe_control: both for nq states (x: nq x ndim; u: nq x nu; p: nq x ndim; v: nq). */
+int or_num_controls(int id);
+int or_gradient_at(const or_grid *g, int spatial, const double *V, int64_t node, double *p);
+int or_interp_at(const or_grid *g, int spatial, const double *V, const double *x, double *p,
+                 double *v);
+int or_optimal_control(const or_dyn *dyn, int game, const double *x, const double *p, double *u);
+int or_safe_control(const or_grid *g, const or_dyn *dyn, int game, int spatial, const double *V,
+                    const double *x, int64_t nq, double *u, double *p, double *v);
+
 #endif
