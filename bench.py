@@ -66,9 +66,11 @@ def parse():
     ap.add_argument("--polish-shift", type=float, default=-1.0, help="FP64 polish start shift (< 0: automatic)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["dubins", "batch", "serve"], default="dubins",
+    ap.add_argument("--workload", choices=["dubins", "batch", "serve", "control"], default="dubins",
                     help="dubins: the headline single-solve benchmark; batch: the 64-instance mixed batch; "
-                         "serve: a Poisson request stream through the serving context, warm vs cold")
+                         "serve: a Poisson request stream through the serving context, warm vs cold; "
+                         "control: safe-control queries against the converged 101^3 Dubins value function")
+    ap.add_argument("--queries", type=int, default=1 << 20, help="control: query states per batch")
     ap.add_argument("--requests", type=int, default=32, help="serve: number of requests")
     ap.add_argument("--quad-n", type=int, default=25, help="serve: grid side of the 6-D quadrotor requests")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -123,6 +125,8 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
+    if args.workload == "control":
+        return bench_control(args)
     if args.workload == "batch":
         bench_batch(args)
         return
@@ -238,6 +242,60 @@ def main():
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(p, npts, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def bench_control(args):
+    """Safe-control queries (Sec. II-B.2, eq. (uOpt)) against the converged 101^3 Dubins value
+    function: the WENO5 nodal gradient once, then batches of uniformly drawn states (gradient,
+    value and control per state), timed with events on the library's stream."""
+    import numpy as np
+    import torch
+
+    from paper_1903_07715_amd import hjr
+    from paper_1903_07715_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    p = W.dubins_problem(args.n)
+    g = p.grid
+    lt = torch.tensor(p.l, device=dev)
+    Vt = torch.empty_like(lt)
+    res, st = hjr.solve_device(g, p.dyn, lt, None, Vt, **hjr.problem_options(p, precision=hjr.FP32_POLISH64))
+    log(f"control: value function {res['iterations']}+{res['polish_iterations']} steps, status {st}")
+    nq = args.queries
+    rng = np.random.default_rng(20190318)
+    x = torch.tensor(rng.uniform(g.lo, g.hi, size=(nq, 3)), device=dev)
+    table = torch.empty(4 * g.size, dtype=torch.float64, device=dev)
+    u = torch.empty(nq, dtype=torch.float64, device=dev)
+    pq = torch.empty(3 * nq, dtype=torch.float64, device=dev)
+    vq = torch.empty(nq, dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    with torch.cuda.stream(stream):
+        for _ in range(max(1, args.warmup)):
+            hjr.gradient_device(g, Vt, table, spatial=5, stream=stream)
+            hjr.safe_control_device(g, p.dyn, table, x, u, p=pq, v=vq, stream=stream)
+        e[0].record(stream)
+        for _ in range(args.steps):
+            hjr.gradient_device(g, Vt, table, spatial=5, stream=stream)
+        e[1].record(stream)
+        e[2].record(stream)
+        for _ in range(args.steps):
+            hjr.safe_control_device(g, p.dyn, table, x, u, p=pq, v=vq, stream=stream)
+        e[3].record(stream)
+    torch.cuda.synchronize()
+    grad_ms = e[0].elapsed_time(e[1]) / args.steps
+    q_ms = e[2].elapsed_time(e[3]) / args.steps
+    # algorithmic bytes: the table pass reads V and writes 4 values per node (FP64); a query reads
+    # its state and the 8 cell-corner records (3 gradient components and V), writes u, p and v
+    grad_bytes = g.size * 8 * (1 + 4)
+    q_bytes = nq * (3 * 8 + 8 * 4 * 8 + 8 * (1 + 3 + 1))
+    log(f"gradient pass {grad_ms * 1e3:.1f} us, {nq} queries {q_ms * 1e3:.1f} us")
+    print(json.dumps({"workload": f"safe-control-dubins{args.n}^3-weno5-fp64", "queries": nq,
+                      "queries_per_s": nq / (q_ms / 1e3), "query_batch_us": q_ms * 1e3,
+                      "gradient_pass_us": grad_ms * 1e3, "unit": "queries/s",
+                      "query_algorithmic_gbs": q_bytes / (q_ms / 1e3) / 1e9,
+                      "gradient_algorithmic_gbs": grad_bytes / (grad_ms / 1e3) / 1e9,
+                      "peak_hbm_gbs": PEAK_HBM_GBS, "steps": args.steps}), flush=True)
 
 
 def bench_batch(args):

@@ -224,6 +224,41 @@ typedef struct {
 hjr_status hjr_profile_enable(int32_t on);
 hjr_status hjr_profile_read(hjr_profile *out, int32_t reset);
 
+/* ---------------------------------------------------------------------------------------------
+ * Safe control (Sec. II-B.2, eq. (uOpt)): online, the system applies
+ * u*(x) = argmax_u min_d <grad V(x), f(x, u, d)> with V the converged value function (avoid game;
+ * argmin_u max_d for the reach game).  Two calls on device arrays, both asynchronous on `stream`
+ * (NULL: the null stream), neither allocating nor synchronising; the caller owns every array
+ * and must keep it alive until the stream has run the call.
+ * ------------------------------------------------------------------------------------------- */
+
+/* Number of control inputs of a model: 1 (double integrator: u), 1 (Dubins car: turn rate),
+ * 2 (unicycle: turn rate, acceleration), 3 (quadrotor: theta, phi, T); 0 for an unknown id. */
+int32_t hjr_num_controls(int32_t dyn_id);
+
+/* Query table of a value function: for V (FP64 device array, C order, grid->n nodes) writes
+ * table (FP64 device array, npts x (ndim + 1), node-major): table[node * (ndim + 1) + d] =
+ * (D-_d V + D+_d V) / 2 for d < ndim, with the solver's one-sided derivatives (spatial =
+ * HJR_UPWIND1 or HJR_WENO5, the same edge rule), and table[node * (ndim + 1) + ndim] = V at the
+ * node.  One record per node, so a query reads one contiguous record per cell corner.
+ * Errors: HJR_ERR_INVALID_ARG (bad grid or scheme, NULL array), HJR_ERR_UNSUPPORTED (2^29
+ * nodes or more), HJR_ERR_DEVICE (launch failure). */
+hjr_status hjr_gradient_device(const hjr_grid *grid, int32_t spatial, const double *V, double *table,
+                               void *stream);
+
+/* Safe-control queries for nq states x (FP64 device array, nq x ndim, row-major).  For each
+ * state, p = grad V(x) and V(x) by multilinear interpolation of `table` (from
+ * hjr_gradient_device) over the grid cell holding x (a non-periodic coordinate is clamped into
+ * [lo, hi], a periodic one reduced into one period), and u*(x) in closed form: each control
+ * takes the bound that the sign of its coefficient in <p, f> selects (the upper bound when the
+ * coefficient is zero).  Outputs (FP64 device arrays): u (nq x hjr_num_controls), p (nq x ndim;
+ * may be NULL) and v (nq; may be NULL).  A state with a non-finite coordinate gets NaN in every
+ * output.  nq = 0 does nothing.  Errors: HJR_ERR_INVALID_ARG (bad grid, model or game, nq < 0 or
+ * above 2^38, NULL table, x or u), HJR_ERR_DEVICE (launch failure). */
+hjr_status hjr_safe_control_device(const hjr_grid *grid, const hjr_dynamics *dyn, int32_t game,
+                                   const double *table, const double *x, int64_t nq, double *u,
+                                   double *p, double *v, void *stream);
+
 /* Serving context: requests with device arrays are admitted while their working memory fits
  * `hbm_budget_bytes` (0 = 90% of free device memory) and advance together, in the same batched
  * launches, with requests already running; a request that arrives while others run joins at the

@@ -710,6 +710,8 @@ int or_interp_at(const or_grid *g, int spatial, const double *V, const double *x
 {
     if (!grid_ok(g)) return -1;
     int nd = g->ndim;
+    for (int d = 0; d < nd; ++d)
+        if (!isfinite(x[d])) return -1;
     int j[OR_MAXD], jn[OR_MAXD];
     double w[OR_MAXD];
     for (int d = 0; d < nd; ++d) cell_of(g, d, x[d], &j[d], &jn[d], &w[d]);
@@ -798,6 +800,15 @@ int or_safe_control(const or_grid *g, const or_dyn *dyn, int game, int spatial, 
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int64_t q = 0; q < nq; ++q) {
         double pq[OR_MAXD], vq;
+        int finite = 1;
+        for (int d = 0; d < nd; ++d) finite &= isfinite(x[q * nd + d]) ? 1 : 0;
+        if (!finite) {  /* a state with a non-finite coordinate gets NaN outputs */
+            for (int i = 0; i < nu; ++i) u[q * nu + i] = NAN;
+            if (p)
+                for (int d = 0; d < nd; ++d) p[q * nd + d] = NAN;
+            if (v) v[q] = NAN;
+            continue;
+        }
         if (or_interp_at(g, spatial, V, x + q * nd, pq, &vq) != 0) {
             bad = 1;
             continue;

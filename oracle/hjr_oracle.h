@@ -105,7 +105,8 @@ int or_threads(void);
  * cell (non-periodic coordinates clamped into [lo, hi], periodic ones wrapped).
  * or_optimal_control: u* = argmax_u min_d <p, f> (avoid) / argmin_u max_d (reach) by
  * enumerating the corners of the control box; on ties the later corner wins.
- * or_safe_control: both for nq states (x: nq x ndim; u: nq x nu; p: nq x ndim; v: nq). */
+ * or_safe_control: both for nq states (x: nq x ndim; u: nq x nu; p: nq x ndim; v: nq); a state
+ * with a non-finite coordinate gets NaN in every output (or_interp_at rejects it). */
 int or_num_controls(int id);
 int or_gradient_at(const or_grid *g, int spatial, const double *V, int64_t node, double *p);
 int or_interp_at(const or_grid *g, int spatial, const double *V, const double *x, double *p,

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhjr.so")
-SOURCES = ["hjr_kernels.hip", "hjr_api.hip"]
+SOURCES = ["hjr_kernels.hip", "hjr_control.hip", "hjr_api.hip"]
 ARCH = "gfx950"
 
 

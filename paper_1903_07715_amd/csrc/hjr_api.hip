@@ -32,6 +32,7 @@
 
 #include "../../include/hjr.h"
 #include "fastdiv.hpp"
+#include "hjr_control.hpp"
 #include "hjr_kernels.hpp"
 
 namespace hjr {
@@ -99,6 +100,8 @@ static int dyn_nparams(int id)
     }
 }
 
+static hjr_status validate_grid(const hjr_grid *g, int spatial, uint64_t *npts_out);
+
 static hjr_status validate(const hjr_grid *g, const hjr_dynamics *dy, int spatial, uint64_t *npts_out)
 {
     if (!g || !dy) return fail(HJR_ERR_INVALID_ARG, "grid and dynamics must not be NULL");
@@ -130,6 +133,15 @@ static hjr_status validate(const hjr_grid *g, const hjr_dynamics *dy, int spatia
             return fail(HJR_ERR_INVALID_ARG, "bad quadrotor parameters");
         break;
     }
+    return validate_grid(g, spatial, npts_out);
+}
+
+static hjr_status validate_grid(const hjr_grid *g, int spatial, uint64_t *npts_out)
+{
+    if (!g) return fail(HJR_ERR_INVALID_ARG, "grid must not be NULL");
+    if (g->ndim < 1 || g->ndim > HJR_MAX_DIM) return fail(HJR_ERR_INVALID_ARG, "ndim %d out of range", g->ndim);
+    if (spatial != HJR_UPWIND1 && spatial != HJR_WENO5)
+        return fail(HJR_ERR_INVALID_ARG, "bad spatial scheme %d", spatial);
     uint64_t N = 1;
     for (int d = 0; d < g->ndim; ++d) {
         const int minn = spatial == HJR_WENO5 ? 7 : 3;
@@ -342,20 +354,11 @@ static Layout plan_layout(const Request &r, bool own_io)
 
 static size_t request_bytes(const Request &r, bool own_io) { return plan_layout(r, own_io).total; }
 
-// Fill the Inst descriptor and the coordinate tables (host staging `tab64`, `tab32`).
-static void build_inst(Request &r, char *base, const Layout &L, std::vector<double> &tab64,
-                       std::vector<float> &tab32, SolveState *state_dev)
+// Grid part of an instance descriptor: sizes, strides, division constants, spacings.
+static void fill_grid(const hjr_grid &g, uint64_t npts, Inst &I)
 {
-    Inst &I = r.inst;
-    std::memset(&I, 0, sizeof I);
-    const hjr_grid &g = r.grid;
     I.ndim = g.ndim;
-    I.dyn = r.dyn.id;
-    I.spatial = r.opts.spatial;
-    I.temporal = r.opts.temporal;
-    I.game = r.opts.game;
-    I.nstages = r.opts.temporal == HJR_TVDRK3 ? 3 : 1;
-    I.npts = (uint32_t)r.npts;
+    I.npts = (uint32_t)npts;
     I.periodic = g.periodic_mask;
     uint32_t s = 1;
     for (int d = g.ndim - 1; d >= 0; --d) {
@@ -374,6 +377,22 @@ static void build_inst(Request &r, char *base, const Layout &L, std::vector<doub
         I.eps0_64[d] = 4e-18 * dx * dx;
         I.eps0_32[d] = std::max((float)I.eps0_64[d], FLT_MIN);  // kept normal in FP32
     }
+}
+
+// Fill the Inst descriptor and the coordinate tables (host staging `tab64`, `tab32`).
+static void build_inst(Request &r, char *base, const Layout &L, std::vector<double> &tab64,
+                       std::vector<float> &tab32, SolveState *state_dev)
+{
+    Inst &I = r.inst;
+    std::memset(&I, 0, sizeof I);
+    const hjr_grid &g = r.grid;
+    I.ndim = g.ndim;
+    I.dyn = r.dyn.id;
+    I.spatial = r.opts.spatial;
+    I.temporal = r.opts.temporal;
+    I.game = r.opts.game;
+    I.nstages = r.opts.temporal == HJR_TVDRK3 ? 3 : 1;
+    fill_grid(g, r.npts, I);
     double c[8];
     make_constants(r.dyn, c);
     for (int i = 0; i < 8; ++i) {
@@ -1427,6 +1446,63 @@ hjr_status hjr_stage_device(const hjr_grid *grid, const hjr_dynamics *dyn, int32
     if (e != hipSuccess) return fail(HJR_ERR_DEVICE, "stage launch failed: %s", hipGetErrorString(e));
     const bool last = temporal == HJR_EULER || k == 2;
     if (delta_out && last) *delta_out = __builtin_bit_cast(double, after.delta_bits);
+    return HJR_OK;
+}
+
+int32_t hjr_num_controls(int32_t dyn_id)
+{
+    switch (dyn_id) {
+    case HJR_DYN_DOUBLE_INTEGRATOR: return 1;
+    case HJR_DYN_DUBINS3: return 1;
+    case HJR_DYN_UNICYCLE4: return 2;
+    case HJR_DYN_QUAD6: return 3;
+    default: return 0;
+    }
+}
+
+hjr_status hjr_gradient_device(const hjr_grid *grid, int32_t spatial, const double *V, double *table, void *stream)
+{
+    uint64_t N = 0;
+    hjr_status s = validate_grid(grid, spatial, &N);
+    if (s != HJR_OK) return s;
+    if (!V || !table) return fail(HJR_ERR_INVALID_ARG, "NULL array");
+    Inst I;
+    std::memset(&I, 0, sizeof I);
+    fill_grid(*grid, N, I);
+    hipError_t e = launch_gradient(I, spatial, V, table, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(HJR_ERR_DEVICE, "gradient launch failed: %s", hipGetErrorString(e));
+    return HJR_OK;
+}
+
+hjr_status hjr_safe_control_device(const hjr_grid *grid, const hjr_dynamics *dyn, int32_t game, const double *table,
+                                   const double *x, int64_t nq, double *u, double *p, double *v, void *stream)
+{
+    uint64_t N = 0;
+    hjr_status s = validate(grid, dyn, HJR_UPWIND1, &N);
+    if (s != HJR_OK) return s;
+    if (game != HJR_AVOID && game != HJR_REACH) return fail(HJR_ERR_INVALID_ARG, "bad game %d", game);
+    if (nq < 0 || nq > ((int64_t)1 << 38)) return fail(HJR_ERR_INVALID_ARG, "query count %lld out of range", (long long)nq);
+    if (nq == 0) return HJR_OK;
+    if (!table || !x || !u) return fail(HJR_ERR_INVALID_ARG, "NULL array");
+    CtlGrid G;
+    std::memset(&G, 0, sizeof G);
+    G.ndim = grid->ndim;
+    G.npts = (uint32_t)N;
+    G.periodic = grid->periodic_mask;
+    uint32_t st = 1;
+    for (int d = grid->ndim - 1; d >= 0; --d) {
+        G.n[d] = grid->n[d];
+        G.stride[d] = st;
+        st *= (uint32_t)grid->n[d];
+        G.lo[d] = grid->lo[d];
+        G.dx[d] = grid_dx(*grid, d);
+    }
+    CtlModel M;
+    std::memset(&M, 0, sizeof M);
+    M.game = game;
+    for (int i = 0; i < dyn->n_params && i < 16; ++i) M.q[i] = dyn->params[i];
+    hipError_t e = launch_control(G, M, dyn->id, table, x, nq, u, p, v, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(HJR_ERR_DEVICE, "control launch failed: %s", hipGetErrorString(e));
     return HJR_OK;
 }
 

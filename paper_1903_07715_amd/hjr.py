@@ -29,7 +29,8 @@ CONV_PER_STEP, CONV_PER_INTERVAL = 0, 1
 EXPORTED = ["hjr_abi_version", "hjr_default_options", "hjr_status_string", "hjr_last_error",
             "hjr_device_count", "hjr_solve", "hjr_solve_device", "hjr_batch_solve", "hjr_cfl_dt",
             "hjr_stage_device", "hjr_ctx_create", "hjr_submit", "hjr_poll", "hjr_ctx_drain",
-            "hjr_ctx_get_stats", "hjr_ctx_destroy", "hjr_profile_enable", "hjr_profile_read"]
+            "hjr_ctx_get_stats", "hjr_ctx_destroy", "hjr_profile_enable", "hjr_profile_read",
+            "hjr_num_controls", "hjr_gradient_device", "hjr_safe_control_device"]
 
 
 class Grid_(C.Structure):
@@ -108,6 +109,7 @@ def load():
         lib.hjr_status_string.argtypes = [C.c_int32]
         lib.hjr_last_error.restype = C.c_char_p
         lib.hjr_device_count.restype = C.c_int32
+        lib.hjr_num_controls.restype = C.c_int32
         lib.hjr_solve.argtypes = [P(Grid_), P(Dynamics_), dp, dp, P(Options_), dp, P(Result_)]
         lib.hjr_solve_device.argtypes = [P(Grid_), P(Dynamics_), vp, vp, P(Options_), vp, vp, P(Result_)]
         lib.hjr_batch_solve.argtypes = [C.c_int32, P(Problem_)]
@@ -122,8 +124,13 @@ def load():
         lib.hjr_ctx_destroy.argtypes = [vp]
         lib.hjr_profile_enable.argtypes = [C.c_int32]
         lib.hjr_profile_read.argtypes = [P(Profile_), C.c_int32]
+        lib.hjr_num_controls.argtypes = [C.c_int32]
+        lib.hjr_gradient_device.argtypes = [P(Grid_), C.c_int32, vp, vp, vp]
+        lib.hjr_safe_control_device.argtypes = [P(Grid_), P(Dynamics_), C.c_int32, vp, vp, C.c_int64, vp, vp, vp,
+                                                vp]
         for name in EXPORTED:
-            if name not in ("hjr_status_string", "hjr_last_error", "hjr_abi_version", "hjr_device_count"):
+            if name not in ("hjr_status_string", "hjr_last_error", "hjr_abi_version", "hjr_device_count",
+                            "hjr_num_controls"):
                 getattr(lib, name).restype = C.c_int32
         _lib = lib
     return _lib
@@ -279,6 +286,39 @@ def stage_device(grid, dyn, stage, dt, Vs, Vn, l, out, game=AVOID, spatial=WENO5
     _check(st)
     last = temporal == EULER or stage == 3
     return delta.value if last else None
+
+
+def num_controls(dyn) -> int:
+    return int(load().hjr_num_controls(dyn.id))
+
+
+def _check_f64_dev(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or t.dtype.itemsize != 8 or not t.is_contiguous()):
+            raise ValueError("device arrays must be contiguous FP64 GPU tensors")
+
+
+def gradient_device(grid, V, table, spatial=WENO5, stream=None) -> None:
+    """hjr_gradient_device: query table (npts x (ndim + 1): gradient components, then V) of V."""
+    _check_f64_dev(V, table)
+    if V.numel() != grid.size or table.numel() != (grid.ndim + 1) * grid.size:
+        raise ValueError("array sizes do not match the grid")
+    _check(load().hjr_gradient_device(C.byref(grid_struct(grid)), spatial, _tptr(V), _tptr(table),
+                                      _stream_ptr(stream)))
+
+
+def safe_control_device(grid, dyn, table, x, u, p=None, v=None, game=AVOID, stream=None) -> None:
+    """hjr_safe_control_device on device tensors: x (nq x ndim) -> u (nq x nu), optional p, v."""
+    _check_f64_dev(table, x, u, p, v)
+    nq = x.shape[0] if x.dim() > 1 else x.numel() // grid.ndim
+    if x.numel() != nq * grid.ndim or u.numel() != nq * num_controls(dyn):
+        raise ValueError("query array sizes do not match")
+    if table.numel() != (grid.ndim + 1) * grid.size:
+        raise ValueError("the table does not match the grid")
+    if (p is not None and p.numel() != nq * grid.ndim) or (v is not None and v.numel() != nq):
+        raise ValueError("output array sizes do not match")
+    _check(load().hjr_safe_control_device(C.byref(grid_struct(grid)), C.byref(dyn_struct(dyn)), game, _tptr(table),
+                                          _tptr(x), nq, _tptr(u), _tptr(p), _tptr(v), _stream_ptr(stream)))
 
 
 def profile_enable(on: bool = True) -> None:

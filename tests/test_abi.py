@@ -142,3 +142,32 @@ def test_product_path_has_no_cpu_fallback():
     for f in os.listdir(os.path.join(ROOT, "paper_1903_07715_amd", "csrc")):
         txt = open(os.path.join(ROOT, "paper_1903_07715_amd", "csrc", f)).read()
         assert "hjr_oracle" not in txt and "or_solve" not in txt
+
+
+def test_num_controls():
+    lib = hjr.load()
+    assert [lib.hjr_num_controls(i) for i in (1, 2, 3, 4, 9)] == [1, 1, 2, 3, 0]
+
+
+def test_safe_control_arguments_rejected_before_device_work():
+    """Every argument check of the two safe-control calls runs before any device work, so these
+    calls (with host pointers that must never be dereferenced) return errors on a CPU host."""
+    lib = hjr.load()
+    g = W.Grid((11, 11, 11), (-1,) * 3, (1,) * 3, (False, False, True))
+    gs = C.byref(hjr.grid_struct(g))
+    dub = C.byref(hjr.dyn_struct(W.dubins3()))
+    fake = C.c_void_p(16)  # never dereferenced: every call below fails validation first
+    assert lib.hjr_gradient_device(gs, 3, fake, fake, None) == hjr.ERR_INVALID_ARG
+    assert lib.hjr_gradient_device(gs, hjr.WENO5, None, fake, None) == hjr.ERR_INVALID_ARG
+    small = C.byref(hjr.grid_struct(W.Grid((5, 11, 11), (-1,) * 3, (1,) * 3)))
+    assert lib.hjr_gradient_device(small, hjr.WENO5, fake, fake, None) == hjr.ERR_INVALID_ARG
+    assert lib.hjr_gradient_device(None, hjr.WENO5, fake, fake, None) == hjr.ERR_INVALID_ARG
+    sc = lib.hjr_safe_control_device
+    assert sc(gs, dub, 2, fake, fake, 4, fake, None, None, None) == hjr.ERR_INVALID_ARG      # game
+    assert sc(gs, dub, hjr.AVOID, fake, fake, -1, fake, None, None, None) == hjr.ERR_INVALID_ARG
+    assert sc(gs, dub, hjr.AVOID, None, fake, 4, fake, None, None, None) == hjr.ERR_INVALID_ARG
+    assert sc(gs, dub, hjr.AVOID, fake, None, 4, fake, None, None, None) == hjr.ERR_INVALID_ARG
+    assert sc(gs, dub, hjr.AVOID, fake, fake, 4, None, None, None, None) == hjr.ERR_INVALID_ARG
+    di = C.byref(hjr.dyn_struct(W.double_integrator()))
+    assert sc(gs, di, hjr.AVOID, fake, fake, 4, fake, None, None, None) == hjr.ERR_INVALID_ARG   # ndim
+    assert sc(gs, dub, hjr.AVOID, fake, fake, 0, fake, None, None, None) == hjr.OK             # no queries
