@@ -97,6 +97,8 @@ static int dyn_ndim(int id)
     case 2: return 3;
     case 3: return 4;
     case 4: return 6;
+    case 5: return 4;
+    case 6: return 2;
     default: return -1;
     }
 }
@@ -108,6 +110,8 @@ static int dyn_nparams(int id)
     case 2: return 4;
     case 3: return 4;
     case 4: return 9;
+    case 5: return 6;
+    case 6: return 6;
     default: return -1;
     }
 }
@@ -139,6 +143,18 @@ int or_flow(const or_dyn *dyn, const double *x, const double *u, const double *d
         f[3] = q[0] * tan(u[0]) + d[0];
         f[4] = -q[0] * tan(u[1]) + d[1];
         f[5] = u[2] / q[1] - q[0] + d[2];
+        return 0;
+    case 5: /* near-hover quadrotor (Sec. V, eq. (Quad10D_dyn)), one horizontal subsystem:
+             * (p, v, theta, omega), u = S, q = {g, d0, d1, n0, S_max, dbar} */
+        f[0] = x[1] + d[0];
+        f[1] = q[0] * tan(x[2]);
+        f[2] = -q[2] * x[2] + x[3];
+        f[3] = -q[1] * x[2] + q[3] * u[0];
+        return 0;
+    case 6: /* near-hover quadrotor, vertical subsystem: (p_z, v_z), u = T_z,
+             * q = {g, k_T, m, T_min, T_max, dbar_z} */
+        f[0] = x[1] + d[0];
+        f[1] = q[1] / q[2] * u[0] - q[0];
         return 0;
     default:
         return -1;
@@ -182,6 +198,14 @@ static int control_corners(const or_dyn *dyn, double u[][3])
                 }
         return c;
     }
+    case 5:
+        u[0][0] = -q[4];
+        u[1][0] = q[4];
+        return 2;
+    case 6:
+        u[0][0] = q[3];
+        u[1][0] = q[4];
+        return 2;
     default:
         return 0;
     }
@@ -195,6 +219,11 @@ static int disturbance_corners(const or_dyn *dyn, double d[][3])
     case 1:
         d[0][0] = -q[2];
         d[1][0] = q[2];
+        return 2;
+    case 5:
+    case 6:
+        d[0][0] = -q[5];
+        d[1][0] = q[5];
         return 2;
     case 2:
     case 3: {
@@ -660,6 +689,8 @@ int or_num_controls(int id)
     case 2: return 1;
     case 3: return 2;
     case 4: return 3;
+    case 5: return 1;
+    case 6: return 1;
     default: return -1;
     }
 }

@@ -41,7 +41,13 @@ typedef struct {
  *  4 planar-attitude quadrotor [px, py, pz, vx, vy, vz]: p' = v, vx' = g tan(theta) + dx,
  *      vy' = -g tan(phi) + dy, vz' = T/m - g + dz; |theta| <= theta_max, |phi| <= phi_max,
  *      T in [Tmin, Tmax], |d_i| <= dbar_i.
- *      params = {g, m, phi_max, theta_max, Tmin, Tmax, dbar_x, dbar_y, dbar_z}          */
+ *      params = {g, m, phi_max, theta_max, Tmin, Tmax, dbar_x, dbar_y, dbar_z}
+ *  5 near-hover quadrotor of Sec. V (eq. (Quad10D_dyn)), one horizontal subsystem
+ *      [p, v, theta, omega]: p' = v + d, v' = g tan(theta), theta' = -d1 theta + omega,
+ *      omega' = -d0 theta + n0 S; |S| <= S_max, |d| <= dbar.
+ *      params = {g, d0, d1, n0, S_max, dbar}
+ *  6 near-hover quadrotor, vertical subsystem [p_z, v_z]: p_z' = v_z + d, v_z' = (k_T/m) T - g;
+ *      T in [T_min, T_max], |d| <= dbar.   params = {g, k_T, m, T_min, T_max, dbar}           */
 typedef struct {
     int32_t id;
     int32_t n_params;
@@ -100,7 +106,7 @@ int or_solve(const or_grid *g, const or_dyn *dyn, const double *l, const double 
 int or_threads(void);
 
 /* Safe control (Sec. II-B.2, eq. (uOpt)).  or_num_controls: number of control inputs of a model
- * (1, 1, 2, 3 for ids 1-4; -1 otherwise).  or_gradient_at: p = (D- + D+)/2 at a node.
+ * (1, 1, 2, 3, 1, 1 for ids 1-6; -1 otherwise).  or_gradient_at: p = (D- + D+)/2 at a node.
  * or_interp_at: p and V at a state x by multilinear interpolation of the nodal values over x's
  * cell (non-periodic coordinates clamped into [lo, hi], periodic ones wrapped).
  * or_optimal_control: u* = argmax_u min_d <p, f> (avoid) / argmin_u max_d (reach) by

@@ -26,9 +26,13 @@ DYN_DOUBLE_INTEGRATOR = 1
 DYN_DUBINS3 = 2
 DYN_UNICYCLE4 = 3
 DYN_QUAD6 = 4
+DYN_QUAD10_XY = 5
+DYN_QUAD10_Z = 6
 
-DYN_NDIM = {DYN_DOUBLE_INTEGRATOR: 2, DYN_DUBINS3: 3, DYN_UNICYCLE4: 4, DYN_QUAD6: 6}
-DYN_NPARAMS = {DYN_DOUBLE_INTEGRATOR: 3, DYN_DUBINS3: 4, DYN_UNICYCLE4: 4, DYN_QUAD6: 9}
+DYN_NDIM = {DYN_DOUBLE_INTEGRATOR: 2, DYN_DUBINS3: 3, DYN_UNICYCLE4: 4, DYN_QUAD6: 6, DYN_QUAD10_XY: 4,
+            DYN_QUAD10_Z: 2}
+DYN_NPARAMS = {DYN_DOUBLE_INTEGRATOR: 3, DYN_DUBINS3: 4, DYN_UNICYCLE4: 4, DYN_QUAD6: 9, DYN_QUAD10_XY: 6,
+               DYN_QUAD10_Z: 6}
 
 
 @dataclass(frozen=True)
@@ -123,6 +127,23 @@ def unicycle4(ubar1=1.0, ubar2=0.5, dbar=0.1, box=False) -> Dynamics:
 
 def quad6(m=1.2, dbar=(0.5, 0.5, 0.5), g=9.81, phi_max=0.3, theta_max=0.3, tmin=5.0, tmax=20.0) -> Dynamics:
     return Dynamics(DYN_QUAD6, (g, m, phi_max, theta_max, tmin, tmax) + tuple(dbar))
+
+
+# The 10-D near-hover quadrotor of Sec. V (eq. (Quad10D_dyn)) with the parameters given there:
+# d0 = 10, d1 = 8, n0 = 10, k_T = 4.55, |S_x|, |S_y| <= 10 degrees, 0 <= T_z <= 2g.  It splits
+# into two identical horizontal 4-D subsystems and one vertical 2-D subsystem.
+G = 9.81
+
+
+def quad10_xy(dbar=1.0, g=G, d0=10.0, d1=8.0, n0=10.0, smax=math.radians(10.0)) -> Dynamics:
+    """Horizontal subsystem (p, v, theta, omega): p' = v + d, v' = g tan(theta),
+    theta' = -d1 theta + omega, omega' = -d0 theta + n0 S, |S| <= smax, |d| <= dbar."""
+    return Dynamics(DYN_QUAD10_XY, (g, d0, d1, n0, smax, dbar))
+
+
+def quad10_z(m=5.0, dbar=1.0, g=G, kt=4.55, tmin=0.0, tmax=2 * G) -> Dynamics:
+    """Vertical subsystem (p_z, v_z): p_z' = v_z + d, v_z' = (k_T/m) T - g, T in [tmin, tmax]."""
+    return Dynamics(DYN_QUAD10_Z, (g, kt, m, tmin, tmax, dbar))
 
 
 # --------------------------------------------------------------------------------------------
@@ -249,6 +270,24 @@ def quad6_problem(n=25, m=1.2, dbar=(0.5, 0.5, 0.5), cfl=0.8, target="obstacle")
         g = Grid((n,) * 6, (-5.0, -5.0, -5.0, -3.0, -3.0, -3.0), (5.0, 5.0, 5.0, 3.0, 3.0, 3.0))
         l = box_sdf(g, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), dims=(0, 1, 2))
     return Problem(f"quad{n}", g, quad6(m=m, dbar=dbar), l, spatial=1, temporal=1, cfl=cfl)
+
+
+def quad10_problems(m=5.0, dbar_xy=1.0, dbar_z=1.0, n_xy=31, n_z=101, scheme="upwind") -> list:
+    """The three subsystems of the 10-D near-hover quadrotor (Sec. V) as avoid problems: x and y
+    (identical) with a wall slab |p| <= 1 to stay out of, on p in [-6,6], v in [-4,4],
+    theta in [-0.4,0.4], omega in [-4,4]; z with the floor p_z <= 0 to stay above, on
+    p_z in [-2,8], v_z in [-6,6].  Targets and grids are readings (the paper gives neither).
+    scheme "upwind": first-order upwind + forward Euler at CFL 0.8; "weno": WENO5 + TVD-RK3 at 0.5."""
+    sp, tp, cfl = (1, 1, 0.8) if scheme == "upwind" else (5, 3, 0.5)
+    gxy = Grid((n_xy,) * 4, (-6.0, -4.0, -0.4, -4.0), (6.0, 4.0, 0.4, 4.0))
+    lxy = np.broadcast_to(np.abs(gxy.mesh()[0]) - 1.0, gxy.shape).copy()
+    gz = Grid((n_z, n_z), (-2.0, -6.0), (8.0, 6.0))
+    lz = np.broadcast_to(gz.mesh()[0], gz.shape).copy()
+    out = []
+    for axis in ("x", "y"):
+        out.append(Problem(f"quad10-{axis}{n_xy}", gxy, quad10_xy(dbar_xy), lxy, spatial=sp, temporal=tp, cfl=cfl))
+    out.append(Problem(f"quad10-z{n_z}", gz, quad10_z(m, dbar_z), lz, spatial=sp, temporal=tp, cfl=cfl))
+    return out
 
 
 def batch_problems(count=64, seed=SEED, n2=(51, 201), n3=(41, 121)) -> list:

@@ -84,7 +84,8 @@ def test_periodic_gradient_is_second_order(orc):
 
 @pytest.mark.parametrize("dyn", [W.double_integrator(1.0, 0.8, 0.3), W.double_integrator(1.0, -0.6, 0.1),
                                  W.dubins3(1.0, 1.5, 0.1, 0.2), W.unicycle4(1.0, 0.5, 0.1),
-                                 W.unicycle4(1.0, 0.5, 0.1, box=True), W.quad6(1.2, (0.5, 0.3, 0.4))])
+                                 W.unicycle4(1.0, 0.5, 0.1, box=True), W.quad6(1.2, (0.5, 0.3, 0.4)),
+                                 W.quad10_xy(1.2), W.quad10_z(5.25, 0.7)])
 @pytest.mark.parametrize("game", [AVOID, REACH])
 def test_optimal_control_attains_lattice_optimum(orc, dyn, game):
     """u* attains max_u min_d <p, f> (avoid) or min_u max_d (reach) over dense lattices of the
@@ -96,6 +97,8 @@ def test_optimal_control_attains_lattice_optimum(orc, dyn, game):
         x = rng.uniform(-2, 2, size=dyn.ndim)
         if dyn.id == W.DYN_UNICYCLE4:
             x[3] = rng.uniform(0, 2)
+        if dyn.id == W.DYN_QUAD10_XY:
+            x[2] = rng.uniform(-0.4, 0.4)
         p = rng.normal(size=dyn.ndim)
 
         def inner(u):
@@ -113,6 +116,10 @@ def test_optimal_control_attains_lattice_optimum(orc, dyn, game):
             assert abs(u[0]) <= q[3] + 1e-15 and abs(u[1]) <= q[2] + 1e-15 and q[4] <= u[2] <= q[5]
         elif dyn.id == W.DYN_UNICYCLE4:
             assert abs(u[0]) <= q[0] + 1e-15 and abs(u[1]) <= q[1] + 1e-15
+        elif dyn.id == W.DYN_QUAD10_XY:
+            assert abs(u[0]) <= q[4] + 1e-15
+        elif dyn.id == W.DYN_QUAD10_Z:
+            assert q[3] <= u[0] <= q[4]
         else:
             assert abs(u[0]) <= (q[0] if dyn.id == W.DYN_DOUBLE_INTEGRATOR else q[1]) + 1e-15
 

@@ -115,6 +115,12 @@ def _flow_np(dyn, x, u, d):
         return [q[0] * math.cos(x[2]) + d[0], q[0] * math.sin(x[2]) + d[1], u[0]]
     if dyn.id == W.DYN_UNICYCLE4:
         return [x[3] * math.cos(x[2]) + d[0], x[3] * math.sin(x[2]) + d[1], u[0], u[1]]
+    if dyn.id == W.DYN_QUAD10_XY:  # Sec. V, eq. (Quad10D_dyn), one horizontal subsystem
+        g, d0, d1, n0 = q[0], q[1], q[2], q[3]
+        return [x[1] + d[0], g * math.tan(x[2]), -d1 * x[2] + x[3], -d0 * x[2] + n0 * u[0]]
+    if dyn.id == W.DYN_QUAD10_Z:  # vertical subsystem
+        g, kt, m = q[0], q[1], q[2]
+        return [x[1] + d[0], kt / m * u[0] - g]
     g, m = q[0], q[1]
     return [x[3], x[4], x[5], g * np.tan(u[0]) + d[0], -g * np.tan(u[1]) + d[1], u[2] / m - g + d[2]]
 
@@ -137,6 +143,12 @@ def _lattices(dyn, k=7):
             D = [(R * np.cos(A)).ravel(), (R * np.sin(A)).ravel()]
             return np.stack(np.meshgrid(*U, indexing="ij"), -1).reshape(-1, 2), np.stack(D, -1)
         D = [lin(-q[2], q[2]), lin(-q[2], q[2])]
+    elif dyn.id == W.DYN_QUAD10_XY:
+        U = [lin(-q[4], q[4])]
+        D = [lin(-q[5], q[5])]
+    elif dyn.id == W.DYN_QUAD10_Z:
+        U = [lin(q[3], q[4])]
+        D = [lin(-q[5], q[5])]
     else:
         U = [lin(-q[3], q[3]), lin(-q[2], q[2]), lin(q[4], q[5])]
         D = [lin(-q[6], q[6]), lin(-q[7], q[7]), lin(-q[8], q[8])]
@@ -147,7 +159,7 @@ def _lattices(dyn, k=7):
 
 @pytest.mark.parametrize("dyn", [W.double_integrator(1.0, 0.8, 0.3), W.dubins3(1.0, 1.5, 0.1, 0.2),
                                  W.unicycle4(1.0, 0.5, 0.1), W.unicycle4(1.0, 0.5, 0.1, box=True),
-                                 W.quad6(1.2, (0.5, 0.3, 0.4))])
+                                 W.quad6(1.2, (0.5, 0.3, 0.4)), W.quad10_xy(1.2), W.quad10_z(5.25, 0.7)])
 @pytest.mark.parametrize("game", [AVOID, REACH])
 def test_hamiltonian_equals_lattice_max_min(orc, dyn, game):
     rng = np.random.default_rng(7)
@@ -156,6 +168,8 @@ def test_hamiltonian_equals_lattice_max_min(orc, dyn, game):
         x = rng.uniform(-2, 2, size=dyn.ndim)
         if dyn.id == W.DYN_UNICYCLE4:
             x[3] = rng.uniform(0, 2)
+        if dyn.id == W.DYN_QUAD10_XY:
+            x[2] = rng.uniform(-0.4, 0.4)
         p = rng.normal(size=dyn.ndim)
         H, alpha = orc.hamiltonian(dyn, x, p, game)
         vals = np.empty((len(Ug), len(Dg)))
@@ -446,3 +460,49 @@ def test_nonfinite_input_rejected(orc):
     l[3, 4] = np.nan
     with pytest.raises(FloatingPointError):
         orc.solve(pr.grid, pr.dyn, l, **orc.problem_opts(pr))
+
+
+# ---------------------------------------------------------------------------------------------
+# The 10-D near-hover quadrotor of Sec. V, by subsystem
+# ---------------------------------------------------------------------------------------------
+
+def test_quad10_vertical_closed_form(orc):
+    """Vertical subsystem with the floor p_z <= 0 to stay above: the best the thrust can do is
+    brake at a = (k_T/m) T_max - g while the worst disturbance pushes down at dbar, so the lowest
+    height reached is p_z - max(0, dbar - v_z)^2 / (2a); V* is that height (l = p_z).  The error
+    is first order in the spacing away from the kink and the domain edges."""
+    errs = []
+    for n in (51, 101):
+        pr = W.quad10_problems(m=5.25, dbar_z=0.7, n_xy=7, n_z=n)[2]
+        V, info = orc.solve(pr.grid, pr.dyn, pr.l, max_iter=20000, **orc.problem_opts(pr))
+        assert info["converged"] == 1
+        g, kt, m, tmin, tmax, dbar = pr.dyn.params
+        a = kt / m * tmax - g
+        P, Vz = np.meshgrid(pr.grid.axis(0), pr.grid.axis(1), indexing="ij")
+        Vs = P - np.maximum(0.0, dbar - Vz) ** 2 / (2 * a)
+        mask = (P >= 0.0) & (P <= 5.0) & (np.abs(Vz) <= 4.0) & (np.abs(Vz - dbar) > 4 * pr.grid.spacing(1))
+        errs.append(np.abs(V - Vs)[mask].mean())
+    assert errs[1] < 0.05
+    assert errs[0] / errs[1] > 1.5
+
+
+def test_quad10_horizontal_symmetry_and_warm_start(orc):
+    """Horizontal subsystem on a grid symmetric about the origin with the slab |p| <= 1: the
+    dynamics are odd in (p, v, theta, omega) and the target even, so V(-x) = V(x) to rounding.
+    Warm-starting the larger-disturbance problem from the smaller one's solution recovers the
+    cold solution (Theorem 2: the old problem dominates the new one), and the larger
+    disturbance can only lower V (Prop. 1)."""
+    old = W.quad10_problems(dbar_xy=1.0, n_xy=11, n_z=7)[0]
+    new = W.quad10_problems(dbar_xy=1.5, n_xy=11, n_z=7)[0]
+    opts = orc.problem_opts(old)
+    Vo, io = orc.solve(old.grid, old.dyn, old.l, max_iter=20000, **opts)
+    assert io["converged"] == 1
+    assert np.abs(Vo - Vo[::-1, ::-1, ::-1, ::-1]).max() < 1e-12
+    Vc, ic = orc.solve(new.grid, new.dyn, new.l, max_iter=20000, **opts)
+    Vw, iw = orc.solve(new.grid, new.dyn, new.l, k=Vo, max_iter=20000, **opts)
+    assert ic["converged"] == 1 and iw["converged"] == 1
+    assert np.abs(Vw - Vc).max() < 1e-4
+    # more disturbance: V can only drop.  The two problems take different CFL steps (alpha grows
+    # with dbar), so the comparison is checked away from the extrapolated edge layers.
+    inner = (slice(2, -2),) * 4
+    assert (Vc[inner] <= Vo[inner] + 1e-9).all()
