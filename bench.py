@@ -66,10 +66,11 @@ def parse():
     ap.add_argument("--polish-shift", type=float, default=-1.0, help="FP64 polish start shift (< 0: automatic)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["dubins", "batch", "serve", "control"], default="dubins",
+    ap.add_argument("--workload", choices=["dubins", "batch", "serve", "control", "quad10"], default="dubins",
                     help="dubins: the headline single-solve benchmark; batch: the 64-instance mixed batch; "
                          "serve: a Poisson request stream through the serving context, warm vs cold; "
-                         "control: safe-control queries against the converged 101^3 Dubins value function")
+                         "control: safe-control queries against the converged 101^3 Dubins value function; "
+                         "quad10: the 10-D near-hover quadrotor scenario of Sec. V by subsystem, warm vs cold")
     ap.add_argument("--queries", type=int, default=1 << 20, help="control: query states per batch")
     ap.add_argument("--requests", type=int, default=32, help="serve: number of requests")
     ap.add_argument("--quad-n", type=int, default=25, help="serve: grid side of the 6-D quadrotor requests")
@@ -127,6 +128,8 @@ def main():
         return
     if args.workload == "control":
         return bench_control(args)
+    if args.workload == "quad10":
+        return bench_quad10(args)
     if args.workload == "batch":
         bench_batch(args)
         return
@@ -296,6 +299,52 @@ def bench_control(args):
                       "query_algorithmic_gbs": q_bytes / (q_ms / 1e3) / 1e9,
                       "gradient_algorithmic_gbs": grad_bytes / (grad_ms / 1e3) / 1e9,
                       "peak_hbm_gbs": PEAK_HBM_GBS, "steps": args.steps}), flush=True)
+
+
+def bench_quad10(args):
+    """Sec. V scenario on the 10-D near-hover quadrotor, solved as its x, y (41^4 each) and z
+    (201^2) subsystems: value functions for mass 5 and horizontal disturbance 1, then for the
+    changed problems (mass 5.25 / disturbance 1.5, and mass 4.8 / disturbance 0.95) cold and
+    warm-started from the first, FP32 + FP64 polish, all three subsystems in one batch."""
+    import torch
+
+    from paper_1903_07715_amd import hjr
+    from paper_1903_07715_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    nxy, nz = 41, 201
+
+    def run(probs, ks):
+        ls = [torch.tensor(p.l, device=dev) for p in probs]
+        outs = [torch.empty_like(l) for l in ls]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with hjr.Context(0) as ctx:
+            ts = [ctx.submit(p.grid, p.dyn, l, k, V, **hjr.problem_options(p, max_iter=50000))
+                  for p, l, k, V in zip(probs, ls, ks, outs)]
+            ctx.drain()
+            res = [ctx.poll(t) for t in ts]
+        return outs, res, time.perf_counter() - t0
+
+    base = W.quad10_problems(m=5.0, dbar_xy=1.0, n_xy=nxy, n_z=nz)
+    run(base, [None] * 3)  # warm-up (tuning, first-touch allocation)
+    Vb, rb, tb = run(base, [None] * 3)
+    log(f"quad10 base: {[r['iterations'] + r['polish_iterations'] for _, r in rb]} steps, {tb:.3f} s")
+    out = {"workload": f"quad10-subsystems-xy{nxy}^4-z{nz}^2-upwind-euler-fp32-polish64",
+           "base_steps": [r["iterations"] + r["polish_iterations"] for _, r in rb], "base_seconds": tb}
+    for tag, m, dxy in (("heavier", 5.25, 1.5), ("lighter", 4.8, 0.95)):
+        new = W.quad10_problems(m=m, dbar_xy=dxy, n_xy=nxy, n_z=nz)
+        Vc, rc, tc = run(new, [None] * 3)
+        Vw, rw, tw = run(new, Vb)
+        err = [float((a - b).abs().max()) for a, b in zip(Vw, Vc)]
+        log(f"quad10 {tag}: cold {tc:.3f} s, warm {tw:.3f} s, max |warm - cold| {err}")
+        out[tag] = {"mass": m, "dbar_xy": dxy,
+                    "cold_steps": [r["iterations"] + r["polish_iterations"] for _, r in rc],
+                    "warm_steps": [r["iterations"] + r["polish_iterations"] for _, r in rw],
+                    "cold_seconds": tc, "warm_seconds": tw, "speedup": tc / tw,
+                    "max_abs_warm_minus_cold": err,
+                    "statuses": [s for s, _ in rc] + [s for s, _ in rw]}
+    print(json.dumps(out), flush=True)
 
 
 def bench_batch(args):

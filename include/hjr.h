@@ -98,8 +98,22 @@ typedef struct {
  *  HJR_DYN_QUAD6 [px, py, pz, vx, vy, vz]: p' = v, vx' = g tan(theta) + dx,
  *      vy' = -g tan(phi) + dy, vz' = T/m - g + dz; |theta| <= theta_max, |phi| <= phi_max,
  *      T in [Tmin, Tmax], |d_i| <= dbar_i.
- *      params = {g, m, phi_max, theta_max, Tmin, Tmax, dbar_x, dbar_y, dbar_z} */
-enum { HJR_DYN_DOUBLE_INTEGRATOR = 1, HJR_DYN_DUBINS3 = 2, HJR_DYN_UNICYCLE4 = 3, HJR_DYN_QUAD6 = 4 };
+ *      params = {g, m, phi_max, theta_max, Tmin, Tmax, dbar_x, dbar_y, dbar_z}
+ *  HJR_DYN_QUAD10_XY [p, v, theta, omega]: one horizontal subsystem of the 10-D near-hover
+ *      quadrotor (Sec. V, eq. (Quad10D_dyn)): p' = v + d, v' = g tan(theta),
+ *      theta' = -d1 theta + omega, omega' = -d0 theta + n0 S; |S| <= S_max, |d| <= dbar; the
+ *      theta range of the grid must lie inside (-pi/2, pi/2).
+ *      params = {g, d0, d1, n0, S_max, dbar}
+ *  HJR_DYN_QUAD10_Z [p_z, v_z]: its vertical subsystem: p_z' = v_z + d, v_z' = (k_T/m) T - g;
+ *      T in [T_min, T_max], |d| <= dbar.                    params = {g, k_T, m, T_min, T_max, dbar} */
+enum {
+    HJR_DYN_DOUBLE_INTEGRATOR = 1,
+    HJR_DYN_DUBINS3 = 2,
+    HJR_DYN_UNICYCLE4 = 3,
+    HJR_DYN_QUAD6 = 4,
+    HJR_DYN_QUAD10_XY = 5,
+    HJR_DYN_QUAD10_Z = 6
+};
 
 typedef struct {
     int32_t id;
@@ -233,7 +247,8 @@ hjr_status hjr_profile_read(hjr_profile *out, int32_t reset);
  * ------------------------------------------------------------------------------------------- */
 
 /* Number of control inputs of a model: 1 (double integrator: u), 1 (Dubins car: turn rate),
- * 2 (unicycle: turn rate, acceleration), 3 (quadrotor: theta, phi, T); 0 for an unknown id. */
+ * 2 (unicycle: turn rate, acceleration), 3 (quadrotor: theta, phi, T), 1 (near-hover
+ * horizontal subsystem: S), 1 (near-hover vertical subsystem: T); 0 for an unknown id. */
 int32_t hjr_num_controls(int32_t dyn_id);
 
 /* Query table of a value function: for V (FP64 device array, C order, grid->n nodes) writes

@@ -85,6 +85,8 @@ static int dyn_ndim(int id)
     case HJR_DYN_DUBINS3: return 3;
     case HJR_DYN_UNICYCLE4: return 4;
     case HJR_DYN_QUAD6: return 6;
+    case HJR_DYN_QUAD10_XY: return 4;
+    case HJR_DYN_QUAD10_Z: return 2;
     default: return -1;
     }
 }
@@ -96,6 +98,8 @@ static int dyn_nparams(int id)
     case HJR_DYN_DUBINS3: return 4;
     case HJR_DYN_UNICYCLE4: return 4;
     case HJR_DYN_QUAD6: return 9;
+    case HJR_DYN_QUAD10_XY: return 6;
+    case HJR_DYN_QUAD10_Z: return 6;
     default: return -1;
     }
 }
@@ -131,6 +135,17 @@ static hjr_status validate(const hjr_grid *g, const hjr_dynamics *dy, int spatia
         if (!(q[1] > 0) || q[2] < 0 || q[3] < 0 || q[2] >= 1.5 || q[3] >= 1.5 || q[4] > q[5] || q[6] < 0 ||
             q[7] < 0 || q[8] < 0)
             return fail(HJR_ERR_INVALID_ARG, "bad quadrotor parameters");
+        break;
+    case HJR_DYN_QUAD10_XY: {
+        if (q[3] < 0 || q[4] < 0 || q[5] < 0) return fail(HJR_ERR_INVALID_ARG, "n0, S_max and dbar must be non-negative");
+        const double half_pi = 1.5707963267948966;
+        if (!(g->lo[2] > -half_pi) || !(g->hi[2] < half_pi) || ((g->periodic_mask >> 2) & 1u))
+            return fail(HJR_ERR_INVALID_ARG, "the pitch/roll range must lie inside (-pi/2, pi/2) and not wrap");
+        break;
+    }
+    case HJR_DYN_QUAD10_Z:
+        if (q[1] < 0 || !(q[2] > 0) || q[3] > q[4] || q[5] < 0)
+            return fail(HJR_ERR_INVALID_ARG, "need k_T >= 0, m > 0, T_min <= T_max, dbar >= 0");
         break;
     }
     return validate_grid(g, spatial, npts_out);
@@ -305,6 +320,21 @@ static void make_constants(const hjr_dynamics &dy, double c[8])
         c[7] = std::max(std::fabs(c[2]), std::fabs(c[3]));
         break;
     }
+    case HJR_DYN_QUAD10_XY:
+        c[0] = q[0];          // g
+        c[1] = q[1];          // d0
+        c[2] = q[2];          // d1
+        c[3] = q[3] * q[4];   // n0 S_max
+        c[4] = q[5];          // dbar
+        break;
+    case HJR_DYN_QUAD10_Z: {
+        const double g = q[0], a = q[1] / q[2];
+        c[0] = a * q[4] - g;
+        c[1] = a * q[3] - g;
+        c[2] = q[5];
+        c[3] = std::max(std::fabs(c[0]), std::fabs(c[1]));
+        break;
+    }
     }
 }
 
@@ -416,6 +446,9 @@ static void build_inst(Request &r, char *base, const Layout &L, std::vector<doub
             tab64[off + j] = std::cos(th);
             tab64[off + nt + j] = std::sin(th);
         }
+    } else if (r.dyn.id == HJR_DYN_QUAD10_XY) {
+        I.trig_off = off;  // tan of the pitch/roll coordinate
+        for (int j = 0; j < g.n[2]; ++j) tab64[off + j] = std::tan(tab64[I.coord_off[2] + j]);
     }
     tab32.resize(tab64.size());
     for (size_t i = 0; i < tab64.size(); ++i) tab32[i] = (float)tab64[i];
@@ -1456,6 +1489,8 @@ int32_t hjr_num_controls(int32_t dyn_id)
     case HJR_DYN_DUBINS3: return 1;
     case HJR_DYN_UNICYCLE4: return 2;
     case HJR_DYN_QUAD6: return 3;
+    case HJR_DYN_QUAD10_XY: return 1;
+    case HJR_DYN_QUAD10_Z: return 1;
     default: return 0;
     }
 }

@@ -70,6 +70,8 @@ template <> struct NumControls<kDynDI> { static constexpr int value = 1; };
 template <> struct NumControls<kDynDubins> { static constexpr int value = 1; };
 template <> struct NumControls<kDynUnicycle> { static constexpr int value = 2; };
 template <> struct NumControls<kDynQuad> { static constexpr int value = 3; };
+template <> struct NumControls<kDynQ10XY> { static constexpr int value = 1; };
+template <> struct NumControls<kDynQ10Z> { static constexpr int value = 1; };
 
 // u* for gradient p.  sg = +1 (avoid: maximise) or -1 (reach: minimise); a control's bound
 // follows the sign of sg times its coefficient in <p, f>, the upper bound when that is zero.
@@ -85,6 +87,10 @@ __device__ __forceinline__ void optimal_control(const CtlModel &M, const double 
     } else if constexpr (DYN == kDynUnicycle) {  // theta' = u1, v' = u2; q = {ubar1, ubar2, ...}
         u[0] = sg * p[2] >= 0.0 ? q[0] : -q[0];
         u[1] = sg * p[3] >= 0.0 ? q[1] : -q[1];
+    } else if constexpr (DYN == kDynQ10XY) {  // omega' = -d0 theta + n0 S; q = {g, d0, d1, n0, S_max, dbar}
+        u[0] = sg * (q[3] * p[3]) >= 0.0 ? q[4] : -q[4];
+    } else if constexpr (DYN == kDynQ10Z) {  // v_z' = (k_T/m) T - g; q = {g, k_T, m, T_min, T_max, dbar}
+        u[0] = sg * (q[1] / q[2] * p[1]) >= 0.0 ? q[4] : q[3];
     } else {  // vx' = g tan(theta), vy' = -g tan(phi), vz' = T/m - g; q = {g, m, phi_max, theta_max, Tmin, Tmax, ...}
         u[0] = sg * (q[0] * p[3]) >= 0.0 ? q[3] : -q[3];
         u[1] = sg * -(q[0] * p[4]) >= 0.0 ? q[2] : -q[2];
@@ -197,6 +203,12 @@ hipError_t launch_control(const CtlGrid &G, const CtlModel &M, int dyn, const do
         break;
     case kDynQuad:
         hipLaunchKernelGGL(control_kernel<kDynQuad>, g, dim3(kBlock), 0, s, G, M, table, x, nq, u, p, v);
+        break;
+    case kDynQ10XY:
+        hipLaunchKernelGGL(control_kernel<kDynQ10XY>, g, dim3(kBlock), 0, s, G, M, table, x, nq, u, p, v);
+        break;
+    case kDynQ10Z:
+        hipLaunchKernelGGL(control_kernel<kDynQ10Z>, g, dim3(kBlock), 0, s, G, M, table, x, nq, u, p, v);
         break;
     default: return hipErrorInvalidValue;
     }

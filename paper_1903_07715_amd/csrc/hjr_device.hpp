@@ -20,7 +20,7 @@ constexpr int kMaxDim = 6;
 constexpr int kBlock = 256;        // threads per workgroup
 constexpr int kFusedNpt = 4;       // nodes per thread of the fused (all-model) stage kernel
 
-enum : int { kDynDI = 1, kDynDubins = 2, kDynUnicycle = 3, kDynQuad = 4 };
+enum : int { kDynDI = 1, kDynDubins = 2, kDynUnicycle = 3, kDynQuad = 4, kDynQ10XY = 5, kDynQ10Z = 6 };
 enum : int { kUpwind1 = 1, kWeno5 = 5 };
 enum : int { kEuler = 1, kRK3 = 3 };
 
@@ -333,6 +333,8 @@ __device__ __forceinline__ void line_derivs(const T *u, int j, int n, bool perio
 //   Unicycle: c0 = ubar1, c1 = ubar2, c2 = dbar, c3 = shape (0 disk, 1 box)
 //   Quad    : c0 = g tan(theta_max), c1 = g tan(phi_max), c2 = Tmax/m - g, c3 = Tmin/m - g,
 //             c4..c6 = dbar_x..z, c7 = max(|c2|, |c3|)
+//   Q10 XY  : c0 = g, c1 = d0, c2 = d1, c3 = n0 S_max, c4 = dbar (near-hover horizontal)
+//   Q10 Z   : c0 = (k_T/m) T_max - g, c1 = (k_T/m) T_min - g, c2 = dbar, c3 = max(|c0|, |c1|)
 // sgn = +1 for the avoid game, -1 for reach: control terms enter as +sgn*|.|, disturbance
 // terms as -sgn*|.|.
 // ---------------------------------------------------------------------------------------------
@@ -366,6 +368,27 @@ __device__ __forceinline__ T hamiltonian(const Inst &I, const T *__restrict__ ta
         alpha[3] = u2;
         T dist = F::c(I, 3) != T(0) ? dd * (fabs(p[0]) + fabs(p[1])) : dd * sqrt(p[0] * p[0] + p[1] * p[1]);
         return v * (p[0] * cs + p[1] * sn) + sgn * (u1 * fabs(p[2]) + u2 * fabs(p[3]) - dist);
+    } else if constexpr (DYN == kDynQ10XY) {
+        // c0 = g, c1 = d0, c2 = d1, c3 = n0 S_max, c4 = dbar; the table holds tan(theta)
+        T v = ldg(tab, I.coord_off[1] + idx[1]);
+        T th = ldg(tab, I.coord_off[2] + idx[2]);
+        T tn = ldg(tab, I.trig_off + idx[2]);
+        T om = ldg(tab, I.coord_off[3] + idx[3]);
+        T f1 = F::c(I, 0) * tn, f2 = om - F::c(I, 2) * th, f3 = -F::c(I, 1) * th;
+        T ns = F::c(I, 3), dd = F::c(I, 4);
+        alpha[0] = fabs(v) + dd;
+        alpha[1] = fabs(f1);
+        alpha[2] = fabs(f2);
+        alpha[3] = fabs(f3) + ns;
+        return p[0] * v + p[1] * f1 + p[2] * f2 + p[3] * f3 + sgn * (ns * fabs(p[3]) - dd * fabs(p[0]));
+    } else if constexpr (DYN == kDynQ10Z) {
+        // c0 = (k_T/m) T_max - g, c1 = (k_T/m) T_min - g, c2 = dbar, c3 = max(|c0|, |c1|)
+        T vz = ldg(tab, I.coord_off[1] + idx[1]);
+        alpha[0] = fabs(vz) + F::c(I, 2);
+        alpha[1] = F::c(I, 3);
+        // the thrust picks T_max or T_min by the sign of p_vz (avoid: maximise)
+        T thrust = (sgn * p[1] > T(0)) ? p[1] * F::c(I, 0) : p[1] * F::c(I, 1);
+        return p[0] * vz + thrust - sgn * F::c(I, 2) * fabs(p[0]);
     } else {
         T vx = ldg(tab, I.coord_off[3] + idx[3]);
         T vy = ldg(tab, I.coord_off[4] + idx[4]);
@@ -391,6 +414,8 @@ template <> struct DynDim<kDynDI> { static constexpr int value = 2; };
 template <> struct DynDim<kDynDubins> { static constexpr int value = 3; };
 template <> struct DynDim<kDynUnicycle> { static constexpr int value = 4; };
 template <> struct DynDim<kDynQuad> { static constexpr int value = 6; };
+template <> struct DynDim<kDynQ10XY> { static constexpr int value = 4; };
+template <> struct DynDim<kDynQ10Z> { static constexpr int value = 2; };
 
 template <int NDIM>
 __device__ __forceinline__ void unflatten(const Inst &I, uint32_t node, int *idx)

@@ -167,6 +167,10 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const Inst *__restrict__ 
         case kDynUnicycle * 8 + kWeno5: stage_tile<T, kDynUnicycle, kWeno5, kFusedNpt>(I, tl.start, stage, dt, red); break;
         case kDynQuad * 8 + kUpwind1: stage_tile<T, kDynQuad, kUpwind1, kFusedNpt>(I, tl.start, stage, dt, red); break;
         case kDynQuad * 8 + kWeno5: stage_tile<T, kDynQuad, kWeno5, kFusedNpt>(I, tl.start, stage, dt, red); break;
+        case kDynQ10XY * 8 + kUpwind1: stage_tile<T, kDynQ10XY, kUpwind1, kFusedNpt>(I, tl.start, stage, dt, red); break;
+        case kDynQ10XY * 8 + kWeno5: stage_tile<T, kDynQ10XY, kWeno5, kFusedNpt>(I, tl.start, stage, dt, red); break;
+        case kDynQ10Z * 8 + kUpwind1: stage_tile<T, kDynQ10Z, kUpwind1, kFusedNpt>(I, tl.start, stage, dt, red); break;
+        case kDynQ10Z * 8 + kWeno5: stage_tile<T, kDynQ10Z, kWeno5, kFusedNpt>(I, tl.start, stage, dt, red); break;
         default: break;
         }
     }
@@ -342,6 +346,8 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const Inst *__restrict__ i
         case kDynDI: rate = rate_of<kDynDI>(I, node); break;
         case kDynDubins: rate = rate_of<kDynDubins>(I, node); break;
         case kDynUnicycle: rate = rate_of<kDynUnicycle>(I, node); break;
+        case kDynQ10XY: rate = rate_of<kDynQ10XY>(I, node); break;
+        case kDynQ10Z: rate = rate_of<kDynQ10Z>(I, node); break;
         default: rate = rate_of<kDynQuad>(I, node); break;
         }
     }
@@ -487,6 +493,10 @@ static void launch_one_npt(int dyn, int spatial, dim3 g, hipStream_t s, const In
     case kDynUnicycle * 8 + kWeno5: HJR_ONE(kDynUnicycle, kWeno5); break;
     case kDynQuad * 8 + kUpwind1: HJR_ONE(kDynQuad, kUpwind1); break;
     case kDynQuad * 8 + kWeno5: HJR_ONE(kDynQuad, kWeno5); break;
+    case kDynQ10XY * 8 + kUpwind1: HJR_ONE(kDynQ10XY, kUpwind1); break;
+    case kDynQ10XY * 8 + kWeno5: HJR_ONE(kDynQ10XY, kWeno5); break;
+    case kDynQ10Z * 8 + kUpwind1: HJR_ONE(kDynQ10Z, kUpwind1); break;
+    case kDynQ10Z * 8 + kWeno5: HJR_ONE(kDynQ10Z, kWeno5); break;
     default: break;
     }
 #undef HJR_ONE

@@ -27,6 +27,8 @@ def _cases():
                             (False, False, True, False)), W.unicycle4(1.0, 0.5, 0.1)),
         ("quad", W.Grid((7, 7, 8, 7, 7, 9), (-5.0, -5.0, -5.0, -3.0, -3.0, -3.0), (5.0, 5.0, 5.0, 3.0, 3.0, 3.0)),
          W.quad6(1.2, (0.5, 0.3, 0.4))),
+        ("quad10-xy", W.Grid((9, 8, 11, 7), (-6.0, -4.0, -0.4, -4.0), (6.0, 4.0, 0.4, 4.0)), W.quad10_xy(1.2)),
+        ("quad10-z", W.Grid((37, 31), (-2.0, -6.0), (8.0, 6.0)), W.quad10_z(5.25, 0.7)),
     ]
 
 
@@ -39,6 +41,10 @@ def _coef(dyn, p):
         return p[:, 2:3]
     if dyn.id == W.DYN_UNICYCLE4:
         return p[:, 2:4]
+    if dyn.id == W.DYN_QUAD10_XY:
+        return q[3] * p[:, 3:4]
+    if dyn.id == W.DYN_QUAD10_Z:
+        return q[1] / q[2] * p[:, 1:2]
     return np.stack([q[0] * p[:, 3], -q[0] * p[:, 4], p[:, 5]], 1)
 
 
@@ -50,6 +56,10 @@ def _bounds(dyn):
         return [(-q[1], q[1])]
     if dyn.id == W.DYN_UNICYCLE4:
         return [(-q[0], q[0]), (-q[1], q[1])]
+    if dyn.id == W.DYN_QUAD10_XY:
+        return [(-q[4], q[4])]
+    if dyn.id == W.DYN_QUAD10_Z:
+        return [(q[3], q[4])]
     return [(-q[3], q[3]), (-q[2], q[2]), (q[4], q[5])]
 
 

@@ -31,12 +31,16 @@ def _stage_cases():
     dub = W.Grid((19, 17, 23), (-5.0, -5.0, -math.pi), (5.0, 5.0, math.pi), (False, False, True))
     uni = W.Grid((9, 11, 13, 8), (-5.0, -5.0, -math.pi, 0.0), (5.0, 5.0, math.pi, 2.0), (False, False, True, False))
     quad = W.Grid((7, 7, 8, 7, 9, 7), (-6, -6, -6, -3, -3, -3), (6, 6, 6, 3, 3, 3))
+    q10xy = W.Grid((9, 8, 11, 7), (-6.0, -4.0, -0.4, -4.0), (6.0, 4.0, 0.4, 4.0))
+    q10z = W.Grid((37, 31), (-2.0, -6.0), (8.0, 6.0))
     return [
         ("di", di, W.double_integrator(1.0, 0.8, 0.3)),
         ("dubins", dub, W.dubins3(1.0, 1.5, 0.1, 0.05)),
         ("unicycle", uni, W.unicycle4(1.0, 0.5, 0.1)),
         ("unicycle-box", uni, W.unicycle4(1.0, 0.5, 0.1, box=True)),
         ("quad", quad, W.quad6(1.2, (0.5, 0.3, 0.4))),
+        ("quad10-xy", q10xy, W.quad10_xy(1.2)),
+        ("quad10-z", q10z, W.quad10_z(5.25, 0.7)),
     ]
 
 

@@ -1,0 +1,55 @@
+"""The 10-D near-hover quadrotor of Sec. V, solved by subsystem on the GPU (two identical
+horizontal 4-D subsystems and the vertical 2-D one), against the oracle: the scenario of the
+section (mass 5 -> 5.25, horizontal disturbance bound 1 -> 1.5) cold and warm-started from the
+previous value function, in FP64 (same steps as the oracle) and in the default FP32 + FP64
+polish; and the three subsystems advanced together in one batch give the results they give
+alone, bitwise."""
+import numpy as np
+import pytest
+
+from paper_1903_07715_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _scenario(n_xy=11, n_z=51):
+    old = W.quad10_problems(m=5.0, dbar_xy=1.0, n_xy=n_xy, n_z=n_z)
+    new = W.quad10_problems(m=5.25, dbar_xy=1.5, n_xy=n_xy, n_z=n_z)
+    return old[1:], new[1:]  # x and y are the same problem; y and z are solved
+
+
+@pytest.mark.parametrize("which", [0, 1], ids=["xy", "z"])
+def test_quad10_fp64_cold_and_warm_match_oracle(gpu, hjrlib, orc, which):
+    old, new = _scenario()
+    po, pn = old[which], new[which]
+    print(f"[quad10] {pn.name} nodes={pn.grid.size}", flush=True)
+    opts = hjrlib.problem_options(po, precision=hjrlib.FP64)
+    Vo, ro, so = hjrlib.solve(po.grid, po.dyn, po.l, None, **opts)
+    Oo, io = orc.solve(po.grid, po.dyn, po.l, max_iter=20000, **orc.problem_opts(po))
+    assert so == hjrlib.OK and io["converged"] == 1
+    assert ro["iterations"] == io["steps"]
+    assert np.abs(Vo - Oo).max() <= 1e-9 * (1 + np.abs(Oo).max())
+    Vw, rw, sw = hjrlib.solve(pn.grid, pn.dyn, pn.l, Vo, **opts)
+    Ow, iw = orc.solve(pn.grid, pn.dyn, pn.l, k=Oo, max_iter=20000, **orc.problem_opts(pn))
+    assert sw == hjrlib.OK and iw["converged"] == 1
+    assert rw["iterations"] == iw["steps"]
+    assert np.abs(Vw - Ow).max() <= 1e-9 * (1 + np.abs(Ow).max())
+
+
+def test_quad10_default_precision_and_batch(gpu, hjrlib, orc):
+    old, new = _scenario()
+    alone = []
+    for pn in new:
+        V, r, st = hjrlib.solve(pn.grid, pn.dyn, pn.l, None, **hjrlib.problem_options(pn))
+        assert st == hjrlib.OK
+        Ov, io = orc.solve(pn.grid, pn.dyn, pn.l, max_iter=20000, **orc.problem_opts(pn))
+        band = 1e-4 * np.abs(pn.l).max()
+        assert np.abs(V - Ov).max() <= band
+        assert np.sum(((V <= 0) != (Ov <= 0)) & (np.abs(Ov) > band)) == 0
+        alone.append((V, r))
+    Vs, rs, sts = hjrlib.batch_solve([(p.grid, p.dyn) for p in new], [p.l for p in new], [None] * len(new),
+                                     [hjrlib.problem_options(p) for p in new])
+    for (Va, ra), V, r, st in zip(alone, Vs, rs, sts):
+        assert st == hjrlib.OK
+        assert (r["iterations"], r["polish_iterations"]) == (ra["iterations"], ra["polish_iterations"])
+        assert np.array_equal(V, Va)
