@@ -136,7 +136,8 @@ typedef struct {
     int32_t steps_per_sync; /* time steps launched between host checks; 0 = adaptive */
     double cfl;             /* in (0, 1]; default 0.5 */
     double tol;             /* > 0; default 1e-6 */
-    double tol_fp32;        /* FP32-phase threshold; 0 = max(tol, 8 ulp_fp32(max |l|)) */
+    double tol_fp32;        /* FP32-phase threshold; 0 = max(tol, k ulp_fp32(max |l|)), k = 3 before the
+                               FP64 polish, 8 for HJR_FP32 alone */
     double polish_shift;    /* < 0 = auto (2 * tol_fp32); the FP64 polish starts at min(l, V32 + shift) */
     double dt_report;       /* interval length of HJR_CONV_PER_INTERVAL; default 0.01 */
     double t_max;           /* > 0: stop at this backward time (finite horizon); default 0 */

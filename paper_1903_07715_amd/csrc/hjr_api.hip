@@ -537,9 +537,12 @@ public:
         m[npt] = m.count(npt) ? std::min(m[npt], us) : us;
         for (int c : kNptCandidates)
             if (!m.count(c)) return;
-        int best = kNptCandidates[0];
+        // another candidate must beat the default by 5% (and the best so far by 2%): near-ties
+        // keep the default, so the choice does not flip with timing noise from run to run
+        const int def = kNptCandidates[0];
+        int best = def;
         for (int c : kNptCandidates)
-            if (m[c] < 0.98 * m[best]) best = c;  // ties go to the earlier candidate
+            if (m[c] < 0.95 * m[def] && m[c] < 0.98 * m[best]) best = c;
         chosen_[k] = best;
         save_file();
     }
@@ -708,7 +711,10 @@ public:
         HJR_HIP(hipMemcpyAsync(d_insts_ + slot, &h_insts_[slot], sizeof(Inst), hipMemcpyHostToDevice, stream_));
         HJR_HIP(hipMemcpyAsync(d_states_ + slot, &h_states_[slot], sizeof(SolveState), hipMemcpyHostToDevice,
                                stream_));
-        HJR_HIP(launch_init(d_insts_, slot, (uint32_t)r->npts, r->l_dev, r->k_dev, r->fp32_first, stream_));
+        // FP32 followed by the FP64 polish: the FP32 phase runs down to 3 spacings, leaving the
+        // polish little to do; FP32 alone stops at 8, clear of its rounding noise
+        const int ulps = !r->fp32_first ? 0 : (r->opts.precision == HJR_FP32_POLISH64 ? 3 : 8);
+        HJR_HIP(launch_init(d_insts_, slot, (uint32_t)r->npts, r->l_dev, r->k_dev, ulps, stream_));
         r->t_start = now_s();
         dirty_ = true;
         return HJR_OK;

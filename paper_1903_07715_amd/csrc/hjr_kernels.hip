@@ -18,7 +18,8 @@ namespace hjr {
 // --------------------------------------------------------------------------------------------
 
 // max that propagates NaN (fmax would drop it and let a blown-up field look converged)
-__device__ __forceinline__ double nanmax(double a, double b) { return (a != a || a > b) ? a : b; }
+template <typename T>
+__device__ __forceinline__ T nanmax(T a, T b) { return (a != a || a > b) ? a : b; }
 
 __device__ __forceinline__ double wave_max(double v)
 {
@@ -112,7 +113,7 @@ __device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int st
     Vn = uniform_ptr(Vn);
     O = uniform_ptr(O);
     const T *l = uniform_ptr(F::l(I));
-    double delta = 0.0;
+    T delta = T(0);  // in the field's precision: the max of exact differences is exact
     // NPT nodes per thread, kBlock apart: independent work the scheduler can interleave
     auto one = [&](uint32_t node) {
         T s;
@@ -129,7 +130,7 @@ __device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int st
             out = fmin(ldg(l, node), vn * T(1.0 / 3.0) + T(2.0 / 3.0) * (s + dt * L));
         }
         stg(O, node, out);
-        if (last) delta = nanmax(delta, (double)fabs(out - vn));
+        if (last) delta = nanmax(delta, T(fabs(out - vn)));
     };
     if (start + (uint32_t)(NPT * kBlock) <= I.npts) {
 #pragma unroll
@@ -141,7 +142,7 @@ __device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int st
             if (node < I.npts) one(node);
         }
     }
-    if (last) block_max_to(delta, &st->delta_bits, red);
+    if (last) block_max_to((double)delta, &st->delta_bits, red);
 }
 
 template <typename T>
@@ -363,7 +364,9 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const Inst *__restrict__ i
 }
 
 // dt, phase threshold and first step size, after init_kernel.
-__global__ void setup_kernel(const Inst *__restrict__ insts, int inst, int fp32_phase)
+// fp32_ulps: 0 for an FP64 phase; otherwise an FP32 phase whose default threshold is that many
+// FP32 spacings at max |l| (or tol, whichever is larger)
+__global__ void setup_kernel(const Inst *__restrict__ insts, int inst, int fp32_ulps)
 {
     if (threadIdx.x != 0) return;
     SolveState *st = insts[inst].state;
@@ -373,6 +376,7 @@ __global__ void setup_kernel(const Inst *__restrict__ insts, int inst, int fp32_
     if (st->dt_max > 0.0 && dt > st->dt_max) dt = st->dt_max;
     st->dt_nom = dt;
     double tol = st->tol_final;
+    const bool fp32_phase = fp32_ulps > 0;
     if (fp32_phase) {
         if (st->tol32_req > 0.0) {
             tol = st->tol32_req;
@@ -380,7 +384,7 @@ __global__ void setup_kernel(const Inst *__restrict__ insts, int inst, int fp32_
             int e;
             (void)frexp(st->max_abs_l, &e);
             const double ulp = ldexp(1.0, e - 24);  // FP32 spacing at max |l|
-            tol = fmax(tol, 8.0 * ulp);
+            tol = fmax(tol, (double)fp32_ulps * ulp);
         }
     }
     st->tol = tol;
@@ -551,13 +555,13 @@ hipError_t launch_interval_end(const Inst *insts, int ninst, hipStream_t s)
 }
 
 hipError_t launch_init(const Inst *insts, int inst, uint32_t npts, const double *l64, const double *k64,
-                       bool fp32, hipStream_t s)
+                       int fp32_ulps, hipStream_t s)
 {
     const int g = (int)((npts + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(init_kernel, dim3(g), dim3(kBlock), 0, s, insts, inst, l64, k64, fp32 ? 1 : 0);
+    hipLaunchKernelGGL(init_kernel, dim3(g), dim3(kBlock), 0, s, insts, inst, l64, k64, fp32_ulps > 0 ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(64), 0, s, insts, inst, fp32 ? 1 : 0);
+    hipLaunchKernelGGL(setup_kernel, dim3(1), dim3(64), 0, s, insts, inst, fp32_ulps);
     return hipGetLastError();
 }
 

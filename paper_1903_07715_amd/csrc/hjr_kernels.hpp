@@ -15,8 +15,10 @@ hipError_t launch_step_end(const Inst *insts, int ninst, hipStream_t s);
 hipError_t launch_interval(bool fp64, const Inst *insts, const Tile *tiles, int ntiles, int max_blocks,
                            hipStream_t s);
 hipError_t launch_interval_end(const Inst *insts, int ninst, hipStream_t s);
+// fp32_ulps: 0 = the solve starts in FP64; > 0 = it starts in FP32 with a default threshold of
+// that many FP32 spacings at max |l|
 hipError_t launch_init(const Inst *insts, int inst, uint32_t npts, const double *l64, const double *k64,
-                       bool fp32, hipStream_t s);
+                       int fp32_ulps, hipStream_t s);
 hipError_t launch_polish(const Inst *insts, int inst, uint32_t npts, int parity32, double shift_req,
                          hipStream_t s);
 hipError_t launch_output(const Inst *insts, int inst, uint32_t npts, bool from32, int parity, double *out,
