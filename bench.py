@@ -207,6 +207,16 @@ def main():
     torch.cuda.synchronize()
     cel = time.perf_counter() - c0
 
+    # the same warm solves through the host-array entry point: l and k go over PCIe in and V
+    # comes back each time (reported beside `value`, never as it)
+    k_h = k_t.cpu().numpy().reshape(p.grid.shape)
+    hjr.solve(p.grid, p.dyn, p.l, k_h, **opts)
+    h0 = time.perf_counter()
+    for i in range(args.steps):
+        hjr.solve(p.grid, p.dyn, p.l, k_h, **opts)
+    hel = time.perf_counter() - h0
+    log(f"host-array warm solves: {hel / args.steps * 1e3:.1f} ms each")
+
     s32 = prof["stage32"]
     launches = sum(s["launches"] for s in s32)
     kms = sum(s["ms"] for s in s32)
@@ -237,6 +247,7 @@ def main():
         "warm_solves_per_s": args.steps / el,
         "event_pass_seconds": pel,
         "cold_solves_per_s": args.steps / cel,
+        "host_io_warm_solves_per_s": args.steps / hel,
         "warm_iterations": [res["iterations"], res["polish_iterations"]],
         "cold_iterations": [cres["iterations"], cres["polish_iterations"]],
         "roofline": roofline,
