@@ -66,11 +66,12 @@ def parse():
     ap.add_argument("--polish-shift", type=float, default=-1.0, help="FP64 polish start shift (< 0: automatic)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["dubins", "batch", "serve", "control", "quad10"], default="dubins",
+    ap.add_argument("--workload", choices=["dubins", "batch", "serve", "control", "quad10", "hbm"], default="dubins",
                     help="dubins: the headline single-solve benchmark; batch: the 64-instance mixed batch; "
                          "serve: a Poisson request stream through the serving context, warm vs cold; "
                          "control: safe-control queries against the converged 101^3 Dubins value function; "
-                         "quad10: the 10-D near-hover quadrotor scenario of Sec. V by subsystem, warm vs cold")
+                         "quad10: the 10-D near-hover quadrotor scenario of Sec. V by subsystem, warm vs cold; "
+                         "hbm: FP32 upwind + Euler steps of the 25^6 quadrotor (the HBM-bound path)")
     ap.add_argument("--queries", type=int, default=1 << 20, help="control: query states per batch")
     ap.add_argument("--requests", type=int, default=32, help="serve: number of requests")
     ap.add_argument("--quad-n", type=int, default=25, help="serve: grid side of the 6-D quadrotor requests")
@@ -130,6 +131,8 @@ def main():
         return bench_control(args)
     if args.workload == "quad10":
         return bench_quad10(args)
+    if args.workload == "hbm":
+        return bench_hbm(args)
     if args.workload == "batch":
         bench_batch(args)
         return
@@ -356,6 +359,49 @@ def bench_quad10(args):
                     "max_abs_warm_minus_cold": err,
                     "statuses": [s for s, _ in rc] + [s for s, _ in rw]}
     print(json.dumps(out), flush=True)
+
+
+def bench_hbm(args):
+    """The HBM-bound path: FP32 first-order upwind + forward Euler steps of the 6-D quadrotor on
+    a 25^6 grid (244 M nodes, about 1 GB per FP32 field, far beyond the 256 MB Infinity Cache).
+    One Euler step must read V and l and write V: 12 algorithmic bytes per node.  The stage
+    kernel's average duration comes from launch-stamped events over a fixed number of steps."""
+    import torch
+
+    from paper_1903_07715_amd import hjr
+    from paper_1903_07715_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    p = W.quad6_problem(args.quad_n)
+    npts = p.grid.size
+    lt = torch.tensor(p.l, device=dev)
+    Vt = torch.empty_like(lt)
+    steps = 40
+    opts = hjr.problem_options(p, precision=hjr.FP32, max_iter=steps)
+    log(f"hbm: quad6 {args.quad_n}^6 = {npts} nodes, {steps} Euler steps per solve")
+    hjr.solve_device(p.grid, p.dyn, lt, None, Vt, **opts)  # warm-up (tuning, first-touch allocation)
+    hjr.solve_device(p.grid, p.dyn, lt, None, Vt, **opts)
+    hjr.profile_read(reset=True)
+    hjr.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res, st = hjr.solve_device(p.grid, p.dyn, lt, None, Vt, **opts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    hjr.profile_enable(False)
+    prof = hjr.profile_read(reset=True)
+    k = prof["stage32"][0]
+    avg_s = k["ms"] / k["launches"] / 1e3
+    gbs = 12.0 * npts / avg_s / 1e9
+    log(f"stage kernel {avg_s * 1e6:.1f} us per launch, {gbs:.0f} GB/s algorithmic")
+    print(json.dumps({"workload": f"quad6-{args.quad_n}^6-upwind-euler-fp32", "nodes": npts,
+                      "steps_per_solve": res["iterations"], "status": st,
+                      "grid_point_updates_per_s": args.steps * res["iterations"] * npts / el,
+                      "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                   "frac": round(gbs / PEAK_HBM_GBS, 4), "avg_launch_us": round(avg_s * 1e6, 1),
+                                   "launches": k["launches"],
+                                   "kernel": "stage_kernel_one<float, Quad6, Upwind1> (upwind + LF + Euler step)"}}),
+          flush=True)
 
 
 def bench_batch(args):

@@ -625,6 +625,7 @@ public:
         if (npt_override_ != 1 && npt_override_ != 2 && npt_override_ != 4 && npt_override_ != 8) npt_override_ = 0;
         if (const char *at = getenv("HJR_AUTOTUNE")) autotune_ = atoi(at) != 0;
         if (const char *gr = getenv("HJR_GRAPHS")) graphs_ = atoi(gr) != 0;
+        if (const char *pb = getenv("HJR_PLANE_BLOCK_BYTES")) plane_block_bytes_ = strtoull(pb, nullptr, 10);
         return HJR_OK;
     }
 
@@ -1028,11 +1029,35 @@ private:
         return HJR_OK;
     }
 
+    // Tiles of each instance, in the order the workgroups of one XCD will sweep them.  In flat
+    // order a node's neighbours along dim 0 are a whole dim-0 plane away, so on a grid whose
+    // planes are larger than plane_block_bytes_ (FP32 field bytes) they have left the caches
+    // before they are read again.  Such grids are visited in chunks of the inner (dims 1..)
+    // index range, two dim-1 strides long, with dim 0 innermost: a node's dim-0 neighbours are
+    // then one chunk away and its dim-1 neighbours inside the chunk.  Every tile start falls in
+    // exactly one (chunk, plane) range, so this is a permutation of the flat-order tiles and
+    // the results do not change.
     void append_tiles(const std::vector<int> &slots, int npt, std::vector<Tile> &out)
     {
-        const uint64_t step = (uint64_t)npt * kBlock;
-        for (int i : slots)
-            for (uint64_t s = 0; s < slots_[i]->npts; s += step) out.push_back(Tile{i, (uint32_t)s, npt});
+        const uint64_t T = (uint64_t)npt * kBlock;
+        for (int i : slots) {
+            const Request *r = slots_[i];
+            const uint64_t N = r->npts;
+            const int n0 = r->grid.n[0];
+            const uint64_t P = N / (uint64_t)n0;  // nodes per dim-0 plane
+            if (r->grid.ndim < 2 || P * 4 <= plane_block_bytes_ || N < 16 * T) {
+                for (uint64_t s = 0; s < N; s += T) out.push_back(Tile{i, (uint32_t)s, npt});
+                continue;
+            }
+            const uint64_t C = std::max<uint64_t>(T, 2 * (P / (uint64_t)r->grid.n[1]));
+            for (uint64_t c0 = 0; c0 < P; c0 += C) {
+                const uint64_t c1 = std::min(P, c0 + C);
+                for (int i0 = 0; i0 < n0; ++i0) {
+                    const uint64_t a = (uint64_t)i0 * P + c0, b = (uint64_t)i0 * P + c1;
+                    for (uint64_t t = (a + T - 1) / T; t * T < b; ++t) out.push_back(Tile{i, (uint32_t)(t * T), npt});
+                }
+            }
+        }
     }
 
     hjr_status upload_tiles(const std::vector<Tile> &a, const std::vector<Tile> &b)
@@ -1124,6 +1149,7 @@ private:
     bool any_interval_ = false;
     bool dirty_ = true;
     int max_blocks_ = 0;
+    uint64_t plane_block_bytes_ = 16ull << 20;  // larger dim-0 planes: blocked tile order
     std::vector<Request *> slots_;
     std::vector<Hist> hist_;
     std::vector<EvRec> evs_;

@@ -301,7 +301,15 @@ __device__ __forceinline__ void line_derivs(const T *u, int j, int n, bool perio
     T r[2 * H];
 #pragma unroll
     for (int o = -H + 1; o <= H; ++o) r[o + H - 1] = u[o + H] - u[o + H - 1];
-    if (!periodic && !inner) {
+    if constexpr (SPATIAL == kUpwind1) {
+        // two differences: at the first node the one before the edge takes the one after it,
+        // at the last node the reverse (n >= 3, so both cannot apply)
+        if (!periodic && !inner) {
+            const T r0 = r[0], r1 = r[1];
+            r[0] = j == 0 ? r1 : r0;
+            r[1] = j == n - 1 ? r0 : r1;
+        }
+    } else if (!periodic && !inner) {
         const int lo = 1 - j, hi = n - 1 - j;  // offsets of the first and last valid difference
         T rlo = r[0], rhi = r[2 * H - 1];
 #pragma unroll

@@ -70,15 +70,27 @@ __device__ __forceinline__ TileRange xcd_range(int ntiles)
 {
     // X groups of workgroups: with 8 or more workgroups, group x is the workgroups that land on
     // XCD x; each group owns one contiguous run of tiles and deals it out round-robin.
+    // These are scalar integer divisions, which the scalar unit runs as long instruction
+    // sequences once per wave; with 8 groups (any launch of 8 or more workgroups) they are
+    // shifts and masks, and with one workgroup per tile every group's count is 0 or 1.
     const int G = gridDim.x, b = blockIdx.x;
-    const int X = G < 8 ? G : 8;
-    const int x = b % X, k = b / X;
-    const int bx = G / X + (x < G % X ? 1 : 0);            // workgroups in group x
-    const int tn = ntiles / X + (x < ntiles % X ? 1 : 0);  // tiles of group x
-    const int t0 = x * (ntiles / X) + min(x, ntiles % X);
+    int x, k, bx, tn, t0;
+    if (G >= 8) {
+        x = b & 7;
+        k = b >> 3;
+        bx = (G >> 3) + (x < (G & 7) ? 1 : 0);            // workgroups in group x
+        tn = (ntiles >> 3) + (x < (ntiles & 7) ? 1 : 0);  // tiles of group x
+        t0 = x * (ntiles >> 3) + min(x, ntiles & 7);
+    } else {
+        x = b;
+        k = 0;
+        bx = 1;
+        tn = ntiles / G + (x < ntiles % G ? 1 : 0);
+        t0 = x * (ntiles / G) + min(x, ntiles % G);
+    }
     TileRange r;
     r.first = t0 + k;
-    r.count = k < tn ? (tn - k + bx - 1) / bx : 0;
+    r.count = k >= tn ? 0 : (bx == tn ? 1 : (tn - k + bx - 1) / bx);
     r.step = bx;
     return r;
 }

@@ -224,11 +224,13 @@ def test_device_entry_point_matches_host_entry_point(gpu, hjrlib):
 
 
 @pytest.mark.parametrize("env", [{"HJR_GRAPHS": "1"}, {"HJR_NPT": "1"}, {"HJR_NPT": "2"}, {"HJR_NPT": "8"},
-                                 {"HJR_FUSED": "1"}, {"HJR_MAX_BLOCKS": "64"}, {"HJR_AUTOTUNE": "0"}],
+                                 {"HJR_FUSED": "1"}, {"HJR_MAX_BLOCKS": "64"}, {"HJR_AUTOTUNE": "0"},
+                                 {"HJR_PLANE_BLOCK_BYTES": "0"}, {"HJR_PLANE_BLOCK_BYTES": "0", "HJR_NPT": "1"}],
                          ids=lambda e: ",".join(f"{k}={v}" for k, v in e.items()))
 def test_launch_configurations_agree_bitwise(gpu, hjrlib, monkeypatch, env):
-    """Graph replay vs direct launches, every nodes-per-thread variant, the fused kernel and a
-    persistent grid give bitwise the same solve: the per-node arithmetic is the same in all."""
+    """Graph replay vs direct launches, every nodes-per-thread variant, the fused kernel, a
+    persistent grid and the plane-blocked tile order give bitwise the same solve: the per-node
+    arithmetic is the same in all."""
     p = W.dubins_problem(31)
     q = W.di_box_problem(61)
     ref = [hjrlib.solve(x.grid, x.dyn, x.l, None, **o) for x, o in
