@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define HJR_ABI_VERSION 1
+#define HJR_ABI_VERSION 2
 #define HJR_MAX_DIM 6
 #define HJR_MAX_PARAMS 16
 
@@ -149,6 +149,11 @@ typedef struct {
                                stalled.  A stalled FP32 phase hands over to the polish; a
                                stalled final phase returns HJR_NOT_CONVERGED with converged = 3.
                                0 = 128; < 0 disables.  HJR_FP64 solves never stop this way. */
+    int32_t brs;            /* 0 (default): the backward reachable tube of the VI, eq. (7): every step
+                               ends with V <- min(l, V).  1: the backward reachable set of Sec. II
+                               at time t_max: the HJ PDE, eq. (5), with no projection.  Needs
+                               t_max > 0, precision HJR_FP64 or HJR_FP32 and no warm start k. */
+    int32_t pad;
 } hjr_options;
 
 typedef struct {

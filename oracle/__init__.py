@@ -41,7 +41,7 @@ class _Dyn(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("game", C.c_int32), ("spatial", C.c_int32), ("temporal", C.c_int32),
-                ("conv_mode", C.c_int32), ("min_each_stage", C.c_int32), ("pad", C.c_int32),
+                ("conv_mode", C.c_int32), ("min_each_stage", C.c_int32), ("brs", C.c_int32),
                 ("cfl", C.c_double), ("tol", C.c_double), ("dt_report", C.c_double),
                 ("t_max", C.c_double), ("dt_max", C.c_double), ("max_iter", C.c_int64)]
 
@@ -123,10 +123,11 @@ def _dyn(d) -> _Dyn:
 
 
 def _opts(spatial=UPWIND1, temporal=EULER, game=AVOID, cfl=0.8, tol=1e-6, conv_mode=CONV_STEP,
-          dt_report=0.01, t_max=0.0, dt_max=0.0, max_iter=200000, min_each_stage=False) -> _Opts:
+          dt_report=0.01, t_max=0.0, dt_max=0.0, max_iter=200000, min_each_stage=False, brs=False) -> _Opts:
     o = _Opts()
     o.game, o.spatial, o.temporal, o.conv_mode = game, spatial, temporal, conv_mode
     o.min_each_stage = int(bool(min_each_stage))
+    o.brs = int(bool(brs))
     o.cfl, o.tol, o.dt_report, o.t_max, o.dt_max, o.max_iter = cfl, tol, dt_report, t_max, dt_max, max_iter
     return o
 

@@ -506,7 +506,8 @@ double or_cfl_dt(const or_grid *g, const or_dyn *dyn, double cfl, double dt_max)
  *   TVD-RK3 (Shu and Osher), stage 1: V1 = Vn + dt L(Vn)
  *                          stage 2: V2 = 3/4 Vn + 1/4 (V1 + dt L(V1))
  *                          stage 3: out = min(l, 1/3 Vn + 2/3 (V2 + dt L(V2)))
- * With min_each_stage the projection onto V <= l is also applied after stages 1 and 2. */
+ * With min_each_stage the projection onto V <= l is also applied after stages 1 and 2; with brs
+ * it is never applied. */
 static double stage_value(const or_grid *g, const or_dyn *dyn, const or_opts *o, int stage,
                           double dt, const double *Vs, const double *Vn, const double *l,
                           int64_t i)
@@ -515,7 +516,7 @@ static double stage_value(const or_grid *g, const or_dyn *dyn, const or_opts *o,
     double v;
     if (o->temporal == OR_EULER) {
         v = Vs[i] + dt * L;
-        return v < l[i] ? v : l[i];
+        return (!o->brs && l[i] < v) ? l[i] : v;
     }
     if (stage == 1) {
         v = Vs[i] + dt * L;
@@ -528,7 +529,7 @@ static double stage_value(const or_grid *g, const or_dyn *dyn, const or_opts *o,
         return v;
     }
     v = Vn[i] / 3.0 + 2.0 / 3.0 * (Vs[i] + dt * L);
-    return v < l[i] ? v : l[i];
+    return (!o->brs && l[i] < v) ? l[i] : v;
 }
 
 static int opts_ok(const or_opts *o)

@@ -65,7 +65,8 @@ typedef struct {
     int32_t temporal;       /* OR_EULER | OR_RK3 */
     int32_t conv_mode;      /* OR_CONV_STEP | OR_CONV_INTERVAL */
     int32_t min_each_stage; /* 0: project onto V <= l after the full step only */
-    int32_t pad;
+    int32_t brs;            /* 1: no projection at all (the backward reachable set of Sec. II,
+                               i.e. the HJ PDE of eq. (5) without the min with l of eq. (7)) */
     double cfl;
     double tol;
     double dt_report;       /* interval length in OR_CONV_INTERVAL mode */

@@ -421,6 +421,7 @@ static void build_inst(Request &r, char *base, const Layout &L, std::vector<doub
     I.spatial = r.opts.spatial;
     I.temporal = r.opts.temporal;
     I.game = r.opts.game;
+    I.brs = r.opts.brs;
     I.nstages = r.opts.temporal == HJR_TVDRK3 ? 3 : 1;
     fill_grid(g, r.npts, I);
     double c[8];
@@ -537,12 +538,12 @@ public:
         m[npt] = m.count(npt) ? std::min(m[npt], us) : us;
         for (int c : kNptCandidates)
             if (!m.count(c)) return;
-        // another candidate must beat the default by 5% (and the best so far by 2%): near-ties
+        // another candidate must beat the default by 8% (and the best so far by 2%): near-ties
         // keep the default, so the choice does not flip with timing noise from run to run
         const int def = kNptCandidates[0];
         int best = def;
         for (int c : kNptCandidates)
-            if (m[c] < 0.95 * m[def] && m[c] < 0.98 * m[best]) best = c;
+            if (m[c] < 0.92 * m[def] && m[c] < 0.98 * m[best]) best = c;
         chosen_[k] = best;
         save_file();
     }
@@ -1174,10 +1175,18 @@ struct ChunkPolicy {
     }
 };
 
-static hjr_status prepare(Request &r, const hjr_grid *g, const hjr_dynamics *dy, const hjr_options *o)
+static hjr_status prepare(Request &r, const hjr_grid *g, const hjr_dynamics *dy, const hjr_options *o,
+                          const void *k)
 {
     hjr_status s = validate_opts(o);
     if (s != HJR_OK) return s;
+    if (o->brs != 0 && o->brs != 1) return fail(HJR_ERR_INVALID_ARG, "brs must be 0 or 1");
+    if (o->brs) {
+        if (!(o->t_max > 0.0)) return fail(HJR_ERR_INVALID_ARG, "the reachable-set mode needs t_max > 0");
+        if (o->precision == HJR_FP32_POLISH64)
+            return fail(HJR_ERR_INVALID_ARG, "the reachable-set mode needs precision HJR_FP64 or HJR_FP32");
+        if (k) return fail(HJR_ERR_INVALID_ARG, "the reachable-set mode takes no warm start");
+    }
     uint64_t N = 0;
     s = validate(g, dy, o->spatial, &N);
     if (s != HJR_OK) return s;
@@ -1244,6 +1253,8 @@ hjr_status hjr_default_options(hjr_options *o)
     o->dt_max = 0.0;
     o->max_iter = 100000;
     o->stall_window = 0;
+    o->brs = 0;
+    o->pad = 0;
     return HJR_OK;
 }
 
@@ -1281,7 +1292,7 @@ hjr_status hjr_solve(const hjr_grid *grid, const hjr_dynamics *dyn, const double
                      const hjr_options *opts, double *V_out, hjr_result *result)
 {
     Request r;
-    hjr_status s = prepare(r, grid, dyn, opts);
+    hjr_status s = prepare(r, grid, dyn, opts, k);
     if (s != HJR_OK) return s;
     if (!l || !V_out) return fail(HJR_ERR_INVALID_ARG, "l and V_out must not be NULL");
     Engine E(1);
@@ -1303,7 +1314,7 @@ hjr_status hjr_solve_device(const hjr_grid *grid, const hjr_dynamics *dyn, const
                             const hjr_options *opts, double *V_dev, void *stream, hjr_result *result)
 {
     Request r;
-    hjr_status s = prepare(r, grid, dyn, opts);
+    hjr_status s = prepare(r, grid, dyn, opts, k_dev);
     if (s != HJR_OK) return s;
     if (!l_dev || !V_dev) return fail(HJR_ERR_INVALID_ARG, "l_dev and V_dev must not be NULL");
     r.l_dev = l_dev;
@@ -1330,7 +1341,7 @@ hjr_status hjr_batch_solve(int32_t count, hjr_problem *problems)
     int sps = 0;
     for (int i = 0; i < count; ++i) {
         hjr_problem &p = problems[i];
-        hjr_status s = prepare(rs[i], &p.grid, &p.dyn, &p.opts);
+        hjr_status s = prepare(rs[i], &p.grid, &p.dyn, &p.opts, p.k);
         if (s == HJR_OK && (!p.l || !p.V_out)) s = fail(HJR_ERR_INVALID_ARG, "problem %d: NULL array", i);
         if (s != HJR_OK) {
             p.status = s;
@@ -1393,7 +1404,7 @@ hjr_status hjr_cfl_dt(const hjr_grid *grid, const hjr_dynamics *dyn, double cfl,
     o.cfl = cfl;
     o.dt_max = dt_max;
     Request r;
-    hjr_status s = prepare(r, grid, dyn, &o);
+    hjr_status s = prepare(r, grid, dyn, &o, nullptr);
     if (s != HJR_OK) return s;
     std::vector<double> zeros(r.npts, 0.0);
     Engine E(1);
@@ -1425,7 +1436,7 @@ hjr_status hjr_stage_device(const hjr_grid *grid, const hjr_dynamics *dyn, int32
     o.temporal = temporal;
     o.precision = precision == HJR_FP32 ? HJR_FP32 : HJR_FP64;
     Request r;
-    hjr_status s = prepare(r, grid, dyn, &o);
+    hjr_status s = prepare(r, grid, dyn, &o, nullptr);
     if (s != HJR_OK) return s;
     const int nst = temporal == HJR_TVDRK3 ? 3 : 1;
     if (stage < 1 || stage > nst) return fail(HJR_ERR_INVALID_ARG, "stage %d out of range 1..%d", stage, nst);
@@ -1689,7 +1700,7 @@ hjr_status hjr_submit(hjr_ctx *ctx, const hjr_grid *grid, const hjr_dynamics *dy
 {
     if (!ctx || !ticket) return fail(HJR_ERR_INVALID_ARG, "ctx and ticket must not be NULL");
     auto r = std::make_unique<Request>();
-    hjr_status s = prepare(*r, grid, dyn, opts);
+    hjr_status s = prepare(*r, grid, dyn, opts, k_dev);
     if (s != HJR_OK) return s;
     if (!l_dev || !V_dev) return fail(HJR_ERR_INVALID_ARG, "l_dev and V_dev must not be NULL");
     r->l_dev = l_dev;

@@ -83,6 +83,7 @@ struct Inst {
     int spatial;
     int temporal;
     int game;
+    int brs;              // 1: no projection onto V <= l (backward reachable set)
     int nstages;
     uint32_t npts;
     uint32_t periodic;

@@ -133,13 +133,15 @@ __device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int st
         T vn = ldg(Vn, node);
         T out;
         if (euler) {
-            out = fmin(ldg(l, node), s + dt * L);
+            out = s + dt * L;
+            if (!I.brs) out = fmin(ldg(l, node), out);
         } else if (stage == 0) {
             out = s + dt * L;
         } else if (stage == 1) {
             out = T(0.75) * vn + T(0.25) * (s + dt * L);
         } else {
-            out = fmin(ldg(l, node), vn * T(1.0 / 3.0) + T(2.0 / 3.0) * (s + dt * L));
+            out = vn * T(1.0 / 3.0) + T(2.0 / 3.0) * (s + dt * L);
+            if (!I.brs) out = fmin(ldg(l, node), out);
         }
         stg(O, node, out);
         if (last) delta = nanmax(delta, T(fabs(out - vn)));

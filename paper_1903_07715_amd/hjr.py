@@ -47,7 +47,8 @@ class Options_(C.Structure):
                 ("precision", C.c_int32), ("conv_mode", C.c_int32), ("steps_per_sync", C.c_int32),
                 ("cfl", C.c_double), ("tol", C.c_double), ("tol_fp32", C.c_double),
                 ("polish_shift", C.c_double), ("dt_report", C.c_double), ("t_max", C.c_double),
-                ("dt_max", C.c_double), ("max_iter", C.c_int64), ("stall_window", C.c_int64)]
+                ("dt_max", C.c_double), ("max_iter", C.c_int64), ("stall_window", C.c_int64),
+                ("brs", C.c_int32), ("pad", C.c_int32)]
 
 
 class Result_(C.Structure):

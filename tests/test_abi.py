@@ -55,7 +55,7 @@ def test_struct_layouts_match_header():
 
 
 def test_defaults_and_strings():
-    assert hjr.abi_version() == 1
+    assert hjr.abi_version() == 2
     o = hjr.options()
     assert (o.spatial, o.temporal, o.precision, o.cfl, o.tol) == (hjr.WENO5, hjr.TVDRK3, hjr.FP32_POLISH64, 0.5, 1e-6)
     lib = hjr.load()
@@ -171,3 +171,25 @@ def test_safe_control_arguments_rejected_before_device_work():
     di = C.byref(hjr.dyn_struct(W.double_integrator()))
     assert sc(gs, di, hjr.AVOID, fake, fake, 4, fake, None, None, None) == hjr.ERR_INVALID_ARG   # ndim
     assert sc(gs, dub, hjr.AVOID, fake, fake, 0, fake, None, None, None) == hjr.OK             # no queries
+
+
+def test_reachable_set_mode_arguments():
+    """The reachable-set mode (no projection) needs a horizon, a plain precision and no warm
+    start; every combination is rejected before any device work."""
+    g = W.Grid((11, 11), (-1, -1), (1, 1))
+    d = W.double_integrator()
+    st, msg = _call_solve(g, d, brs=1, precision=hjr.FP64)
+    assert st == hjr.ERR_INVALID_ARG and "t_max" in msg
+    st, msg = _call_solve(g, d, brs=1, t_max=0.5)  # default precision is FP32 + polish
+    assert st == hjr.ERR_INVALID_ARG and "precision" in msg
+    st, msg = _call_solve(g, d, brs=2, t_max=0.5, precision=hjr.FP64)
+    assert st == hjr.ERR_INVALID_ARG
+    l = np.zeros(g.size)
+    k = np.zeros(g.size)
+    V = np.zeros(g.size)
+    res = hjr.Result_()
+    o = hjr.options(brs=1, t_max=0.5, precision=hjr.FP64)
+    dp = C.POINTER(C.c_double)
+    st = hjr.load().hjr_solve(C.byref(hjr.grid_struct(g)), C.byref(hjr.dyn_struct(d)), l.ctypes.data_as(dp),
+                              k.ctypes.data_as(dp), C.byref(o), V.ctypes.data_as(dp), C.byref(res))
+    assert st == hjr.ERR_INVALID_ARG and "warm" in hjr.last_error()

@@ -506,3 +506,44 @@ def test_quad10_horizontal_symmetry_and_warm_start(orc):
     # with dbar), so the comparison is checked away from the extrapolated edge layers.
     inner = (slice(2, -2),) * 4
     assert (Vc[inner] <= Vo[inner] + 1e-9).all()
+
+
+# ---------------------------------------------------------------------------------------------
+# Backward reachable set (Sec. II): the HJ PDE without the projection onto V <= l
+# ---------------------------------------------------------------------------------------------
+
+def _advection(orc, n, l_fn, T, brs):
+    """Double integrator with no control and no disturbance: x1' = x2, x2' = 0, so the flow
+    moves x1 by x2 t.  By the method of characteristics the reachable set's value at time T is
+    l(x1 + x2 T, x2), and the tube's is the smallest l along the way."""
+    g = W.Grid((n, n), (-1.0, -1.0), (1.0, 1.0))
+    X1, X2 = np.meshgrid(g.axis(0), g.axis(1), indexing="ij")
+    V, info = orc.solve(g, W.double_integrator(0.0, 1.0, 0.0), l_fn(X1, X2), spatial=orc.UPWIND1,
+                        temporal=orc.EULER, cfl=0.8, tol=1e-300, t_max=T, brs=brs)
+    assert info["converged"] == 2 and abs(info["t"] - T) < 1e-9
+    return g, X1, X2, V
+
+
+def test_brs_pure_advection_of_linear_target_is_exact(orc):
+    lin = lambda a, b: 0.3 * a - 0.7 * b + 0.1
+    T = 0.5
+    g, X1, X2, V = _advection(orc, 41, lin, T, True)
+    assert np.abs(V - lin(X1 + X2 * T, X2)).max() < 1e-12
+    # the tube keeps the smallest value along the flow: for a target linear along it, the
+    # smaller of the two end values
+    _, _, _, Vt = _advection(orc, 41, lin, T, False)
+    assert np.abs(Vt - np.minimum(lin(X1, X2), lin(X1 + X2 * T, X2))).max() < 1e-12
+
+
+def test_brs_smooth_target_first_order_and_above_tube(orc):
+    bump = lambda a, b: 0.5 - np.exp(-((a - 0.1) ** 2 + (b + 0.2) ** 2) / 0.1)
+    T = 0.4
+    errs = []
+    for n in (41, 81):
+        g, X1, X2, V = _advection(orc, n, bump, T, True)
+        inner = (np.abs(X1) <= 0.5) & (np.abs(X2) <= 0.5)
+        errs.append(np.abs(V - bump(X1 + X2 * T, X2))[inner].max())
+        _, _, _, Vt = _advection(orc, n, bump, T, False)
+        assert (Vt <= V + 1e-12).all()  # the tube is the minimum over time, so never above the set
+    assert errs[1] < 0.05
+    assert 1.5 < errs[0] / errs[1] < 2.6
