@@ -43,13 +43,14 @@ class _Opts(C.Structure):
     _fields_ = [("game", C.c_int32), ("spatial", C.c_int32), ("temporal", C.c_int32),
                 ("conv_mode", C.c_int32), ("min_each_stage", C.c_int32), ("brs", C.c_int32),
                 ("cfl", C.c_double), ("tol", C.c_double), ("dt_report", C.c_double),
-                ("t_max", C.c_double), ("dt_max", C.c_double), ("max_iter", C.c_int64)]
+                ("t_max", C.c_double), ("dt_max", C.c_double), ("max_iter", C.c_int64),
+                ("discount", C.c_double)]
 
 
 class _Result(C.Structure):
     _fields_ = [("steps", C.c_int64), ("intervals", C.c_int64), ("t", C.c_double),
                 ("last_delta", C.c_double), ("dt", C.c_double), ("converged", C.c_int32),
-                ("pad", C.c_int32)]
+                ("pad", C.c_int32), ("discounted_steps", C.c_int64)]
 
 
 def build(force: bool = False) -> str:
@@ -123,11 +124,13 @@ def _dyn(d) -> _Dyn:
 
 
 def _opts(spatial=UPWIND1, temporal=EULER, game=AVOID, cfl=0.8, tol=1e-6, conv_mode=CONV_STEP,
-          dt_report=0.01, t_max=0.0, dt_max=0.0, max_iter=200000, min_each_stage=False, brs=False) -> _Opts:
+          dt_report=0.01, t_max=0.0, dt_max=0.0, max_iter=200000, min_each_stage=False, brs=False,
+          discount=0.0) -> _Opts:
     o = _Opts()
     o.game, o.spatial, o.temporal, o.conv_mode = game, spatial, temporal, conv_mode
     o.min_each_stage = int(bool(min_each_stage))
     o.brs = int(bool(brs))
+    o.discount = discount
     o.cfl, o.tol, o.dt_report, o.t_max, o.dt_max, o.max_iter = cfl, tol, dt_report, t_max, dt_max, max_iter
     return o
 
@@ -242,7 +245,7 @@ def solve(grid, dyn, l, k=None, **opts):
     if rc:
         raise ValueError(f"or_solve failed ({rc})")
     info = dict(steps=res.steps, intervals=res.intervals, t=res.t, last_delta=res.last_delta, dt=res.dt,
-                converged=res.converged)
+                converged=res.converged, discounted_steps=res.discounted_steps)
     return V, info
 
 

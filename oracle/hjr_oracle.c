@@ -507,15 +507,19 @@ double or_cfl_dt(const or_grid *g, const or_dyn *dyn, double cfl, double dt_max)
  *                          stage 2: V2 = 3/4 Vn + 1/4 (V1 + dt L(V1))
  *                          stage 3: out = min(l, 1/3 Vn + 2/3 (V2 + dt L(V2)))
  * With min_each_stage the projection onto V <= l is also applied after stages 1 and 2; with brs
- * it is never applied. */
+ * it is never applied.  With a discount factor gamma in (0, 1) (discounted reachability,
+ * Sec. II-C: the value one step later enters the dynamic programming principle multiplied by the
+ * per-step factor, the target term not) the value of the full step is multiplied by gamma before
+ * the projection. */
 static double stage_value(const or_grid *g, const or_dyn *dyn, const or_opts *o, int stage,
                           double dt, const double *Vs, const double *Vn, const double *l,
                           int64_t i)
 {
     double L = lf_at(g, dyn, o->game, o->spatial, Vs, i);
+    double gamma = (o->discount > 0.0 && o->discount < 1.0) ? o->discount : 1.0;
     double v;
     if (o->temporal == OR_EULER) {
-        v = Vs[i] + dt * L;
+        v = gamma * (Vs[i] + dt * L);
         return (!o->brs && l[i] < v) ? l[i] : v;
     }
     if (stage == 1) {
@@ -528,7 +532,7 @@ static double stage_value(const or_grid *g, const or_dyn *dyn, const or_opts *o,
         if (o->min_each_stage && l[i] < v) v = l[i];
         return v;
     }
-    v = Vn[i] / 3.0 + 2.0 / 3.0 * (Vs[i] + dt * L);
+    v = gamma * (Vn[i] / 3.0 + 2.0 / 3.0 * (Vs[i] + dt * L));
     return (!o->brs && l[i] < v) ? l[i] : v;
 }
 
@@ -601,7 +605,9 @@ int or_step(const or_grid *g, const or_dyn *dyn, const or_opts *o, const double 
  * Per-step mode stops when max |V^{n+1} - V^n| < tol.  Interval mode (the rule of Sec. IV)
  * takes CFL steps whose sizes are cut so that they end exactly on multiples of dt_report and
  * stops when the largest change of V across one whole interval is below tol.  Both modes also
- * stop at max_iter steps or when t reaches t_max (t_max > 0). */
+ * stop at max_iter steps or when t reaches t_max (t_max > 0).  Discounted reachability (a
+ * discount in (0, 1)) runs the same loop with the discounted step; the first time the test
+ * passes, the discount is set to 1 (annealed) and the loop goes on instead of stopping. */
 int or_solve(const or_grid *g, const or_dyn *dyn, const double *l, const double *k,
              const or_opts *o, double *V, or_result *res)
 {
@@ -609,6 +615,9 @@ int or_solve(const or_grid *g, const or_dyn *dyn, const double *l, const double 
         !(o->tol > 0.0) || !res)
         return -1;
     if (o->conv_mode == OR_CONV_INTERVAL && !(o->dt_report > 0.0)) return -1;
+    or_opts cur = *o;  /* its discount drops to 1 at the anneal */
+    int discounted = o->discount > 0.0 && o->discount < 1.0;
+    int64_t disc_steps = 0;
     int64_t N = grid_points(g);
     for (int64_t i = 0; i < N; ++i) {
         if (!isfinite(l[i]) || (k && !isfinite(k[i]))) return -3;
@@ -637,13 +646,19 @@ int or_solve(const or_grid *g, const or_dyn *dyn, const double *l, const double 
         if (o->t_max > 0.0 && o->t_max - t < dt) dt = o->t_max - t;
         if (o->conv_mode == OR_CONV_INTERVAL && o->dt_report - t_int < dt) dt = o->dt_report - t_int;
         double delta;
-        or_step(g, dyn, o, l, V, dt, Vnext, &delta);
+        or_step(g, dyn, &cur, l, V, dt, Vnext, &delta);
         memcpy(V, Vnext, sizeof(double) * (size_t)N);
         steps += 1;
         t += dt;
         if (o->conv_mode == OR_CONV_STEP) {
             last = delta;
             if (delta < o->tol) {
+                if (discounted) {
+                    discounted = 0;
+                    disc_steps = steps;
+                    cur.discount = 1.0;
+                    continue;
+                }
                 converged = 1;
                 break;
             }
@@ -660,6 +675,12 @@ int or_solve(const or_grid *g, const or_dyn *dyn, const double *l, const double 
                 memcpy(Vstart, V, sizeof(double) * (size_t)N);
                 t_int = 0.0;
                 if (m < o->tol) {
+                    if (discounted) {
+                        discounted = 0;
+                        disc_steps = steps;
+                        cur.discount = 1.0;
+                        continue;
+                    }
                     converged = 1;
                     break;
                 }
@@ -672,6 +693,7 @@ int or_solve(const or_grid *g, const or_dyn *dyn, const double *l, const double 
     res->last_delta = last;
     res->dt = dt_nom;
     res->converged = converged;
+    res->discounted_steps = discounted ? steps : disc_steps;
     free(Vnext);
     free(Vstart);
     return 0;

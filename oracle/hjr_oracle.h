@@ -73,6 +73,9 @@ typedef struct {
     double t_max;           /* 0: infinite horizon */
     double dt_max;          /* 0: no cap (a zero flow field uses dt = 1) */
     int64_t max_iter;
+    double discount;        /* discounted reachability (Sec. II-C): in (0, 1) every step ends with
+                               min(l, discount * V_step); or_solve anneals it to 1 once the change
+                               falls below tol.  0 or 1: none */
 } or_opts;
 
 typedef struct {
@@ -83,6 +86,7 @@ typedef struct {
     double dt;              /* nominal CFL time step */
     int32_t converged;      /* 1 converged, 0 max_iter hit, 2 horizon t_max reached */
     int32_t pad;
+    int64_t discounted_steps;  /* steps taken before the discount was annealed to 1 */
 } or_result;
 
 /* All functions return 0 on success and a negative value on bad arguments. */

@@ -547,3 +547,84 @@ def test_brs_smooth_target_first_order_and_above_tube(orc):
         assert (Vt <= V + 1e-12).all()  # the tube is the minimum over time, so never above the set
     assert errs[1] < 0.05
     assert 1.5 < errs[0] / errs[1] < 2.6
+
+
+# ---------------------------------------------------------------------------------------------
+# Discounted reachability (Sec. II-C): V <- min(l, gamma * V_step), annealed to gamma = 1
+# ---------------------------------------------------------------------------------------------
+
+def test_discount_zero_flow_closed_form(orc):
+    """With no motion at all (Dubins car with zero speed, turn rate and disturbance) the step is
+    the identity, so the discounted iterate is gamma^n l where l > 0 and l elsewhere; the change
+    of step n is gamma^(n-1) (1 - gamma) max l, which fixes the number of discounted steps.  After
+    the anneal the next step changes nothing and the solve stops."""
+    g = W.Grid((9, 10, 8), (-1.0, -1.0, -math.pi), (1.0, 1.0, math.pi), (False, False, True))
+    dyn = W.dubins3(0.0, 0.0, 0.0, 0.0)
+    l = W.smooth_field(g, seed=2)
+    lmax, tol = l.max(), 1e-6
+    for gamma in (0.9, 0.99):
+        n = 1
+        while gamma ** (n - 1) * (1 - gamma) * lmax >= tol:
+            n += 1
+        for temporal in (orc.EULER, orc.RK3):
+            V, info = orc.solve(g, dyn, l, discount=gamma, tol=tol, spatial=orc.UPWIND1, temporal=temporal)
+            assert info["converged"] == 1 and info["discounted_steps"] == n and info["steps"] == n + 1
+            want = np.where(l > 0, gamma ** n * l, l)
+            assert np.abs(V - want).max() <= 1e-13 * lmax
+
+
+def test_discount_scales_the_whole_step_on_linear_data(orc):
+    """Upwind derivatives of linear data are exact (boundaries included) and the dissipation
+    vanishes, so one discounted Euler step of the double integrator on V = a1 x1 + a2 x2 + c is
+    min(l, gamma (V + dt (a1 x2 + b ubar |a2| - dbar |a1|))) exactly (avoid game, eq. (6))."""
+    g = W.Grid((13, 11), (-1.0, -2.0), (1.5, 1.0))
+    ubar, b, dbar = 0.7, 1.3, 0.2
+    dyn = W.double_integrator(ubar, b, dbar)
+    X1, X2 = np.meshgrid(g.axis(0), g.axis(1), indexing="ij")
+    a1, a2, c = 0.8, -1.7, 0.3
+    V = a1 * X1 + a2 * X2 + c
+    l = 0.5 + 0.4 * np.cos(3 * X1) * X2  # binds at some nodes only
+    dt, gamma = 0.01, 0.95
+    out, _ = orc.step(g, dyn, V, l, dt, spatial=orc.UPWIND1, temporal=orc.EULER, discount=gamma)
+    want = np.minimum(l, gamma * (V + dt * (a1 * X2 + b * ubar * abs(a2) - dbar * abs(a1))))
+    assert np.abs(out - want).max() <= 1e-13
+    assert (out == l).any() and (out < l).any()
+
+
+def test_discounted_step_is_a_contraction(orc):
+    """Sec. II-C: discounting makes the dynamic-programming step a contraction.  For the monotone
+    scheme (upwind + Lax-Friedrichs + Euler at CFL <= 1) without boundaries the undiscounted step
+    does not expand max-norm distances, so the discounted one shrinks them by at least gamma;
+    the undiscounted step leaves a constant offset unchanged where the projection is idle."""
+    g, dyn, l = _periodic_di(n=31)
+    dt = orc.cfl_dt(g, dyn, 0.8)
+    rng = np.random.default_rng(11)
+    for gamma in (0.9, 0.5):
+        for _ in range(5):
+            A, B = rng.normal(size=g.shape), rng.normal(size=g.shape)
+            TA, _ = orc.step(g, dyn, A, l, dt, spatial=orc.UPWIND1, temporal=orc.EULER, discount=gamma)
+            TB, _ = orc.step(g, dyn, B, l, dt, spatial=orc.UPWIND1, temporal=orc.EULER, discount=gamma)
+            assert np.abs(TA - TB).max() <= gamma * np.abs(A - B).max() * (1 + 1e-12)
+    big = np.full(g.shape, 1e3)  # the projection never binds
+    A = rng.normal(size=g.shape)
+    TA, _ = orc.step(g, dyn, A, big, dt, spatial=orc.UPWIND1, temporal=orc.EULER, discount=0.9)
+    TB, _ = orc.step(g, dyn, A + 0.25, big, dt, spatial=orc.UPWIND1, temporal=orc.EULER, discount=0.9)
+    assert np.abs((TB - TA) - 0.9 * 0.25).max() <= 1e-12
+
+
+def test_discount_forgets_a_stuck_initialization(orc):
+    """The Sec. IV-B start (k below V* with wrong gradients) stays stuck without a discount; with
+    one the discounted phase converges to the same function as from l (a contraction has one
+    fixed point: both iterates end within tol / (1 - gamma) of it)."""
+    g, dyn, l = _periodic_di(n=41)
+    o = dict(spatial=orc.UPWIND1, temporal=orc.EULER, cfl=0.8, tol=1e-6)
+    k = -l - np.abs(l).max() - 0.1
+    Vs, _ = orc.solve(g, dyn, l, k, max_iter=3000, **o)
+    assert np.all(Vs <= 0)  # stuck: everything unsafe
+    gamma = 0.9
+    Vc, ic = orc.solve(g, dyn, l, None, discount=gamma, **o)
+    Vk, ik = orc.solve(g, dyn, l, k, discount=gamma, **o)
+    assert ic["converged"] == 1 and ik["converged"] == 1
+    assert ic["discounted_steps"] > 0 and ik["discounted_steps"] > 0
+    assert np.abs(Vc - Vk).max() <= 3 * o["tol"] / (1 - gamma)
+    assert np.abs(Vs - Vc).max() > 0.5  # the undiscounted stuck start does not get there
