@@ -40,7 +40,7 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the FP32 stage kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # (scaled by a 1 GiB copy calibration), keyed by a hash of the kernel sources they were taken
 # from: a kernel changed since then reports null.
-MEASURED_TRAFFIC = {"862be83d315cce1d": 9.875e6 + 3.923e6}
+MEASURED_TRAFFIC = {"7e220faf6fe1c363": 9.882e6 + 3.923e6}
 
 
 def kernel_source_hash() -> str:
@@ -66,12 +66,15 @@ def parse():
     ap.add_argument("--polish-shift", type=float, default=-1.0, help="FP64 polish start shift (< 0: automatic)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["dubins", "batch", "serve", "control", "quad10", "hbm"], default="dubins",
+    ap.add_argument("--workload", choices=["dubins", "batch", "serve", "control", "quad10", "hbm", "discount"],
+                    default="dubins",
                     help="dubins: the headline single-solve benchmark; batch: the 64-instance mixed batch; "
                          "serve: a Poisson request stream through the serving context, warm vs cold; "
                          "control: safe-control queries against the converged 101^3 Dubins value function; "
-                         "quad10: the 10-D near-hover quadrotor scenario of Sec. V by subsystem, warm vs cold; "
-                         "hbm: FP32 upwind + Euler steps of the 25^6 quadrotor (the HBM-bound path)")
+                         "quad10: the 10-D near-hover quadrotor scenario of Sec. VI by subsystem, warm vs cold; "
+                         "hbm: FP32 upwind + Euler steps of the 25^6 quadrotor (the HBM-bound path); "
+                         "discount: standard vs warm-started vs discounted solves (Table 1's comparison)")
+    ap.add_argument("--discount", type=float, default=0.999, help="discount: per-step factor (annealed to 1)")
     ap.add_argument("--queries", type=int, default=1 << 20, help="control: query states per batch")
     ap.add_argument("--requests", type=int, default=32, help="serve: number of requests")
     ap.add_argument("--quad-n", type=int, default=25, help="serve: grid side of the 6-D quadrotor requests")
@@ -133,6 +136,8 @@ def main():
         return bench_quad10(args)
     if args.workload == "hbm":
         return bench_hbm(args)
+    if args.workload == "discount":
+        return bench_discount(args)
     if args.workload == "batch":
         bench_batch(args)
         return
@@ -261,6 +266,54 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def bench_discount(args):
+    """Table 1's comparison on two of our problems: standard reachability (from l), warm start
+    (from the solution of a smaller-disturbance problem, exact by Theorem 2) and discounted
+    reachability (Sec. II-C, per-step factor annealed to 1), from l and from the same warm start.
+    Each solve runs once untimed, then once timed; steps and device seconds are reported."""
+    import numpy as np
+    import torch
+
+    from paper_1903_07715_amd import hjr
+    from paper_1903_07715_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    out = {}
+    probs = [("dubins3d-%d^3-weno5-tvdrk3-fp32-polish64" % args.n, W.dubins_problem(args.n, dbar=0.1),
+              W.dubins_problem(args.n, dbar=0.05), dict(precision=hjr.FP32_POLISH64)),
+             ("double-integrator-101^2-upwind-euler-fp64", W.di_box_problem(101, ubar=1.0, dbar=0.1),
+              W.di_box_problem(101, ubar=1.0, dbar=0.05), dict(precision=hjr.FP64))]
+    for name, p, q, extra in probs:
+        opts = hjr.problem_options(p, max_iter=200000, **extra)
+        lt, lq = torch.tensor(p.l, device=dev), torch.tensor(q.l, device=dev)
+        kt, Vt = torch.empty_like(lt), torch.empty_like(lt)
+        hjr.solve_device(q.grid, q.dyn, lq, None, kt, **dict(opts, precision=hjr.FP64))
+        runs = {"standard": (None, 0.0), "warm": (kt, 0.0), "discounted": (None, args.discount),
+                "discounted_warm": (kt, args.discount)}
+        res = {}
+        V = {}
+        for key, (k, gamma) in runs.items():
+            for timed in (False, True):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r, st = hjr.solve_device(p.grid, p.dyn, lt, k, Vt, **dict(opts, discount=gamma))
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+            V[key] = Vt.cpu().numpy()
+            res[key] = {"seconds": el, "steps": r["iterations"] + r["polish_iterations"],
+                        "discounted_steps": r["discounted_iterations"], "status": st}
+            log(f"{name} {key}: {res[key]}")
+        for key in ("warm", "discounted", "discounted_warm"):
+            res[key]["max_abs_diff_vs_standard"] = float(np.abs(V[key] - V["standard"]).max())
+            res[key]["unsafe_set_mismatch_nodes"] = int(np.sum((V[key] <= 0) != (V["standard"] <= 0)))
+        res["discounted_over_warm_steps"] = res["discounted"]["steps"] / res["warm"]["steps"]
+        res["discounted_over_warm_seconds"] = res["discounted"]["seconds"] / res["warm"]["seconds"]
+        res["standard_over_warm_seconds"] = res["standard"]["seconds"] / res["warm"]["seconds"]
+        out[name] = res
+    print(json.dumps({"workload": "standard-vs-warm-vs-discounted", "discount": args.discount, "problems": out}),
+          flush=True)
+
+
 def bench_control(args):
     """Safe-control queries (Sec. II-B.2, eq. (uOpt)) against the converged 101^3 Dubins value
     function: the WENO5 nodal gradient once, then batches of uniformly drawn states (gradient,
@@ -316,7 +369,7 @@ def bench_control(args):
 
 
 def bench_quad10(args):
-    """Sec. V scenario on the 10-D near-hover quadrotor, solved as its x, y (41^4 each) and z
+    """Sec. VI scenario on the 10-D near-hover quadrotor, solved as its x, y (41^4 each) and z
     (201^2) subsystems: value functions for mass 5 and horizontal disturbance 1, then for the
     changed problems (mass 5.25 / disturbance 1.5, and mass 4.8 / disturbance 0.95) cold and
     warm-started from the first, FP32 + FP64 polish, all three subsystems in one batch."""

@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define HJR_ABI_VERSION 2
+#define HJR_ABI_VERSION 3
 #define HJR_MAX_DIM 6
 #define HJR_MAX_PARAMS 16
 
@@ -100,7 +100,7 @@ typedef struct {
  *      T in [Tmin, Tmax], |d_i| <= dbar_i.
  *      params = {g, m, phi_max, theta_max, Tmin, Tmax, dbar_x, dbar_y, dbar_z}
  *  HJR_DYN_QUAD10_XY [p, v, theta, omega]: one horizontal subsystem of the 10-D near-hover
- *      quadrotor (Sec. V, eq. (Quad10D_dyn)): p' = v + d, v' = g tan(theta),
+ *      quadrotor (Sec. VI, eq. (Quad10D_dyn)): p' = v + d, v' = g tan(theta),
  *      theta' = -d1 theta + omega, omega' = -d0 theta + n0 S; |S| <= S_max, |d| <= dbar; the
  *      theta range of the grid must lie inside (-pi/2, pi/2).
  *      params = {g, d0, d1, n0, S_max, dbar}
@@ -154,6 +154,14 @@ typedef struct {
                                at time t_max: the HJ PDE, eq. (5), with no projection.  Needs
                                t_max > 0, precision HJR_FP64 or HJR_FP32 and no warm start k. */
     int32_t pad;
+    double discount;        /* 0 (default) or 1: none.  In (0, 1): discounted reachability (Sec. II-C):
+                               each step ends with V <- min(l, discount * V_step), V_step the
+                               result of the time integrator, which makes the step a contraction
+                               whatever the start; once the change falls below the threshold (or
+                               stalls), the factor is annealed to 1 and the solve goes on as
+                               usual.  Applies to the first phase (rounded to FP32 there when
+                               the precision is HJR_FP32 or HJR_FP32_POLISH64); the FP64 polish is
+                               never discounted.  Not with brs. */
 } hjr_options;
 
 typedef struct {
@@ -168,6 +176,7 @@ typedef struct {
     int32_t converged;          /* 1 converged, 0 max_iter reached, 2 horizon reached,
                                    3 stalled: the change stopped decreasing above tol */
     int32_t pad;
+    int64_t discounted_iterations;  /* steps of the first phase taken with a discount < 1 */
 } hjr_result;
 
 /* Library information and defaults. */

@@ -144,7 +144,7 @@ int or_flow(const or_dyn *dyn, const double *x, const double *u, const double *d
         f[4] = -q[0] * tan(u[1]) + d[1];
         f[5] = u[2] / q[1] - q[0] + d[2];
         return 0;
-    case 5: /* near-hover quadrotor (Sec. V, eq. (Quad10D_dyn)), one horizontal subsystem:
+    case 5: /* near-hover quadrotor (Sec. VI, eq. (Quad10D_dyn)), one horizontal subsystem:
              * (p, v, theta, omega), u = S, q = {g, d0, d1, n0, S_max, dbar} */
         f[0] = x[1] + d[0];
         f[1] = q[0] * tan(x[2]);

@@ -42,7 +42,7 @@ typedef struct {
  *      vy' = -g tan(phi) + dy, vz' = T/m - g + dz; |theta| <= theta_max, |phi| <= phi_max,
  *      T in [Tmin, Tmax], |d_i| <= dbar_i.
  *      params = {g, m, phi_max, theta_max, Tmin, Tmax, dbar_x, dbar_y, dbar_z}
- *  5 near-hover quadrotor of Sec. V (eq. (Quad10D_dyn)), one horizontal subsystem
+ *  5 near-hover quadrotor of Sec. VI (eq. (Quad10D_dyn)), one horizontal subsystem
  *      [p, v, theta, omega]: p' = v + d, v' = g tan(theta), theta' = -d1 theta + omega,
  *      omega' = -d0 theta + n0 S; |S| <= S_max, |d| <= dbar.
  *      params = {g, d0, d1, n0, S_max, dbar}

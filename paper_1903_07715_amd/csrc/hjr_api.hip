@@ -484,6 +484,7 @@ static SolveState initial_state(const Request &r)
     st.conv_mode = r.opts.conv_mode;
     st.stall_window = r.opts.stall_window == 0 ? 128 : (r.opts.stall_window < 0 ? 0 : r.opts.stall_window);
     st.last_delta = INFINITY;
+    st.gamma = r.opts.discount > 0.0 ? r.opts.discount : 1.0;
     st.done = kRunning;  // set properly by setup_kernel
     return st;
 }
@@ -899,6 +900,7 @@ public:
                 res.iterations = r->iters0;
                 res.polish_iterations = st.n;
             }
+            res.discounted_iterations = (r->phase == 0 && st.gamma != 1.0) ? st.n : st.n_disc;
             res.intervals = st.intervals;
             res.t_final = st.t;
             res.last_delta = st.last_delta;
@@ -1187,6 +1189,10 @@ static hjr_status prepare(Request &r, const hjr_grid *g, const hjr_dynamics *dy,
             return fail(HJR_ERR_INVALID_ARG, "the reachable-set mode needs precision HJR_FP64 or HJR_FP32");
         if (k) return fail(HJR_ERR_INVALID_ARG, "the reachable-set mode takes no warm start");
     }
+    if (!(o->discount >= 0.0 && o->discount <= 1.0))
+        return fail(HJR_ERR_INVALID_ARG, "discount must lie in [0, 1]");
+    if (o->brs && o->discount > 0.0 && o->discount < 1.0)
+        return fail(HJR_ERR_INVALID_ARG, "the reachable-set mode is not discounted");
     uint64_t N = 0;
     s = validate(g, dy, o->spatial, &N);
     if (s != HJR_OK) return s;
@@ -1255,6 +1261,7 @@ hjr_status hjr_default_options(hjr_options *o)
     o->stall_window = 0;
     o->brs = 0;
     o->pad = 0;
+    o->discount = 0.0;
     return HJR_OK;
 }
 

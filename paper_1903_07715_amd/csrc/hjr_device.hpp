@@ -57,6 +57,8 @@ struct SolveState {
     int conv_mode;        // 0 per step, 1 per interval
     int check_interval;   // the step just taken closed a report interval
     int phase;            // 0 first phase, 1 FP64 polish
+    double gamma;         // discount factor of the current step (1 = none, always after the anneal)
+    long long n_disc;     // steps of the first phase taken with gamma < 1 (set at the anneal)
 };
 
 // Division by a runtime constant: q = (x * mul) >> (32 + shift), exact for 0 <= x < 2^31.

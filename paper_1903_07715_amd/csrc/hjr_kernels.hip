@@ -125,6 +125,7 @@ __device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int st
     Vn = uniform_ptr(Vn);
     O = uniform_ptr(O);
     const T *l = uniform_ptr(F::l(I));
+    const T gm = (T)st->gamma;  // discount (1 outside discounted reachability: x * 1 == x exactly)
     T delta = T(0);  // in the field's precision: the max of exact differences is exact
     // NPT nodes per thread, kBlock apart: independent work the scheduler can interleave
     auto one = [&](uint32_t node) {
@@ -133,14 +134,14 @@ __device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int st
         T vn = ldg(Vn, node);
         T out;
         if (euler) {
-            out = s + dt * L;
+            out = gm * (s + dt * L);
             if (!I.brs) out = fmin(ldg(l, node), out);
         } else if (stage == 0) {
             out = s + dt * L;
         } else if (stage == 1) {
             out = T(0.75) * vn + T(0.25) * (s + dt * L);
         } else {
-            out = vn * T(1.0 / 3.0) + T(2.0 / 3.0) * (s + dt * L);
+            out = gm * (vn * T(1.0 / 3.0) + T(2.0 / 3.0) * (s + dt * L));
             if (!I.brs) out = fmin(ldg(l, node), out);
         }
         stg(O, node, out);
@@ -251,6 +252,18 @@ __device__ __forceinline__ void note_delta(SolveState *st, double delta, long lo
     if (count - st->n_best >= window) st->done = kStalled;
 }
 
+// Discounted reachability: a first phase that has converged (or stalled) with gamma < 1 goes on
+// undiscounted instead of ending.
+__device__ __forceinline__ void anneal(SolveState *st, long long count)
+{
+    if (st->gamma == 1.0 || (st->done != kConverged && st->done != kStalled)) return;
+    st->gamma = 1.0;
+    st->n_disc = st->n;
+    st->done = kRunning;
+    st->best_delta = INFINITY;
+    st->n_best = count;
+}
+
 __global__ void step_end_kernel(const Inst *__restrict__ insts, int ninst)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -268,6 +281,7 @@ __global__ void step_end_kernel(const Inst *__restrict__ insts, int ninst)
         st->last_delta = delta;
         if (delta < st->tol) st->done = kConverged;
         note_delta(st, delta, st->n);
+        anneal(st, st->n);
         apply_limits(st);
     } else {
         st->t_int += dt;
@@ -318,6 +332,7 @@ __global__ void interval_end_kernel(const Inst *__restrict__ insts, int ninst)
     st->last_delta = d;
     if (d < st->tol) st->done = kConverged;
     note_delta(st, d, st->intervals);
+    anneal(st, st->intervals);
     apply_limits(st);
 }
 
@@ -420,6 +435,10 @@ __global__ void polish_switch_kernel(const Inst *__restrict__ insts, int inst, d
     if (threadIdx.x != 0) return;
     SolveState *st = insts[inst].state;
     st->tol32_req = shift_req >= 0.0 ? shift_req : 2.0 * st->tol;  // reused: the shift
+    if (st->gamma != 1.0) {  // the FP32 phase ended still discounted: the polish is not
+        st->n_disc = st->n;
+        st->gamma = 1.0;
+    }
     st->phase = 1;
     st->parity = 0;
     st->done = kRunning;

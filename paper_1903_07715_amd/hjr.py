@@ -48,14 +48,14 @@ class Options_(C.Structure):
                 ("cfl", C.c_double), ("tol", C.c_double), ("tol_fp32", C.c_double),
                 ("polish_shift", C.c_double), ("dt_report", C.c_double), ("t_max", C.c_double),
                 ("dt_max", C.c_double), ("max_iter", C.c_int64), ("stall_window", C.c_int64),
-                ("brs", C.c_int32), ("pad", C.c_int32)]
+                ("brs", C.c_int32), ("pad", C.c_int32), ("discount", C.c_double)]
 
 
 class Result_(C.Structure):
     _fields_ = [("iterations", C.c_int64), ("polish_iterations", C.c_int64), ("intervals", C.c_int64),
                 ("t_final", C.c_double), ("last_delta", C.c_double), ("dt", C.c_double),
                 ("max_abs_l", C.c_double), ("seconds", C.c_double), ("converged", C.c_int32),
-                ("pad", C.c_int32)]
+                ("pad", C.c_int32), ("discounted_iterations", C.c_int64)]
 
 
 class Problem_(C.Structure):

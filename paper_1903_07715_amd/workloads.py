@@ -129,7 +129,7 @@ def quad6(m=1.2, dbar=(0.5, 0.5, 0.5), g=9.81, phi_max=0.3, theta_max=0.3, tmin=
     return Dynamics(DYN_QUAD6, (g, m, phi_max, theta_max, tmin, tmax) + tuple(dbar))
 
 
-# The 10-D near-hover quadrotor of Sec. V (eq. (Quad10D_dyn)) with the parameters given there:
+# The 10-D near-hover quadrotor of Sec. VI (eq. (Quad10D_dyn)) with the parameters given there:
 # d0 = 10, d1 = 8, n0 = 10, k_T = 4.55, |S_x|, |S_y| <= 10 degrees, 0 <= T_z <= 2g.  It splits
 # into two identical horizontal 4-D subsystems and one vertical 2-D subsystem.
 G = 9.81
@@ -273,7 +273,7 @@ def quad6_problem(n=25, m=1.2, dbar=(0.5, 0.5, 0.5), cfl=0.8, target="obstacle")
 
 
 def quad10_problems(m=5.0, dbar_xy=1.0, dbar_z=1.0, n_xy=31, n_z=101, scheme="upwind") -> list:
-    """The three subsystems of the 10-D near-hover quadrotor (Sec. V) as avoid problems: x and y
+    """The three subsystems of the 10-D near-hover quadrotor (Sec. VI) as avoid problems: x and y
     (identical) with a wall slab |p| <= 1 to stay out of, on p in [-6,6], v in [-4,4],
     theta in [-0.4,0.4], omega in [-4,4]; z with the floor p_z <= 0 to stay above, on
     p_z in [-2,8], v_z in [-6,6].  Targets and grids are readings (the paper gives neither).

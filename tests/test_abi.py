@@ -55,7 +55,7 @@ def test_struct_layouts_match_header():
 
 
 def test_defaults_and_strings():
-    assert hjr.abi_version() == 2
+    assert hjr.abi_version() == 3
     o = hjr.options()
     assert (o.spatial, o.temporal, o.precision, o.cfl, o.tol) == (hjr.WENO5, hjr.TVDRK3, hjr.FP32_POLISH64, 0.5, 1e-6)
     lib = hjr.load()
@@ -193,3 +193,15 @@ def test_reachable_set_mode_arguments():
     st = hjr.load().hjr_solve(C.byref(hjr.grid_struct(g)), C.byref(hjr.dyn_struct(d)), l.ctypes.data_as(dp),
                               k.ctypes.data_as(dp), C.byref(o), V.ctypes.data_as(dp), C.byref(res))
     assert st == hjr.ERR_INVALID_ARG and "warm" in hjr.last_error()
+
+
+def test_discount_arguments():
+    """The discount factor must lie in [0, 1] and is refused in the reachable-set mode; both are
+    rejected before any device work."""
+    g = W.Grid((11, 11), (-1, -1), (1, 1))
+    d = W.double_integrator()
+    for bad in (-0.5, 1.5, float("nan")):
+        st, msg = _call_solve(g, d, discount=bad)
+        assert st == hjr.ERR_INVALID_ARG and "discount" in msg
+    st, msg = _call_solve(g, d, brs=1, t_max=0.5, precision=hjr.FP64, discount=0.99)
+    assert st == hjr.ERR_INVALID_ARG and "discount" in msg

@@ -267,3 +267,52 @@ def test_reachable_set_mode_matches_oracle(gpu, hjrlib, orc, scheme):
     assert (Vt < Vg - 1e-3).any()
     if spatial == 1:
         assert (Vt <= Vg + 1e-12).all()
+
+
+def _periodic_di(n=41):
+    g = W.Grid((n, n), (-1.0, -1.0), (1.0, 1.0), (True, True))
+    return g, W.double_integrator(1.0, 1.0, 0.1), W.box_sdf(g, (0.0, 0.0), (0.2, 0.2))
+
+
+@pytest.mark.parametrize("conv_mode", [0, 1], ids=["per-step", "per-interval"])
+@pytest.mark.parametrize("warm", [False, True], ids=["cold", "stuck-start"])
+def test_discounted_solve_matches_oracle(gpu, hjrlib, orc, warm, conv_mode):
+    """Discounted reachability (factor 0.9 per step, annealed to 1 on convergence) on the
+    periodic double integrator, upwind + Euler, FP64: the same discounted and total step counts
+    and the same values as the oracle, from l and from the stuck start of Sec. IV-B."""
+    g, dyn, l = _periodic_di()
+    k = -l - np.abs(l).max() - 0.1 if warm else None
+    opts = dict(spatial=1, temporal=1, cfl=0.8, tol=1e-6, discount=0.9, conv_mode=conv_mode, dt_report=0.05)
+    print(f"[discount] warm={warm} conv_mode={conv_mode}", flush=True)
+    Vo, io = orc.solve(g, dyn, l, k, **opts)
+    assert io["converged"] == 1 and io["discounted_steps"] > 0
+    Vg, rg, st = hjrlib.solve(g, dyn, l, k, precision=hjrlib.FP64, **opts)
+    assert st == hjrlib.OK and rg["converged"] == 1
+    assert rg["discounted_iterations"] == io["discounted_steps"]
+    assert rg["iterations"] == io["steps"] and rg["intervals"] == io["intervals"]
+    assert np.abs(Vg - Vo).max() <= 1e-9 * np.abs(l).max()
+
+
+def test_discounted_fp32_polish_and_batch(gpu, hjrlib, orc):
+    """The discount in the FP32 phase (factor rounded to FP32), then the FP64 polish: within the
+    FP32 + polish bar of the oracle.  In a batch beside an undiscounted instance each result is
+    bitwise the one it has alone."""
+    g, dyn, l = _periodic_di()
+    opts = dict(spatial=1, temporal=1, cfl=0.8, tol=1e-6, discount=0.9)
+    Vo, io = orc.solve(g, dyn, l, None, **opts)
+    Vg, rg, st = hjrlib.solve(g, dyn, l, None, precision=hjrlib.FP32_POLISH64, **opts)
+    band = 1e-4 * np.abs(l).max()
+    assert st == hjrlib.OK and rg["discounted_iterations"] > 0 and rg["polish_iterations"] >= 1
+    assert np.abs(Vg - Vo).max() <= band
+    assert _sign_mismatch(Vg, Vo, band) == 0
+    p = W.dubins_problem(25)
+    cases = [(g, dyn, l, dict(opts, precision=hjrlib.FP32_POLISH64)),
+             (p.grid, p.dyn, p.l, hjrlib.problem_options(p)),
+             (g, dyn, l, dict(opts, precision=hjrlib.FP64, discount=0.95))]
+    Vs, rs, sts = hjrlib.batch_solve([(c[0], c[1]) for c in cases], [c[2] for c in cases], [None] * 3,
+                                     [c[3] for c in cases])
+    for (gg, dd, ll, o), V, r, st in zip(cases, Vs, rs, sts):
+        Va, ra, sta = hjrlib.solve(gg, dd, ll, None, **o)
+        assert st == sta == hjrlib.OK
+        assert r["discounted_iterations"] == ra["discounted_iterations"]
+        assert np.array_equal(V, Va)

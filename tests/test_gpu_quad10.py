@@ -1,4 +1,4 @@
-"""The 10-D near-hover quadrotor of Sec. V, solved by subsystem on the GPU (two identical
+"""The 10-D near-hover quadrotor of Sec. VI, solved by subsystem on the GPU (two identical
 horizontal 4-D subsystems and the vertical 2-D one), against the oracle: the scenario of the
 section (mass 5 -> 5.25, horizontal disturbance bound 1 -> 1.5) cold and warm-started from the
 previous value function, in FP64 (same steps as the oracle) and in the default FP32 + FP64

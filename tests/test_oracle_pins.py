@@ -115,7 +115,7 @@ def _flow_np(dyn, x, u, d):
         return [q[0] * math.cos(x[2]) + d[0], q[0] * math.sin(x[2]) + d[1], u[0]]
     if dyn.id == W.DYN_UNICYCLE4:
         return [x[3] * math.cos(x[2]) + d[0], x[3] * math.sin(x[2]) + d[1], u[0], u[1]]
-    if dyn.id == W.DYN_QUAD10_XY:  # Sec. V, eq. (Quad10D_dyn), one horizontal subsystem
+    if dyn.id == W.DYN_QUAD10_XY:  # Sec. VI, eq. (Quad10D_dyn), one horizontal subsystem
         g, d0, d1, n0 = q[0], q[1], q[2], q[3]
         return [x[1] + d[0], g * math.tan(x[2]), -d1 * x[2] + x[3], -d0 * x[2] + n0 * u[0]]
     if dyn.id == W.DYN_QUAD10_Z:  # vertical subsystem
@@ -463,7 +463,7 @@ def test_nonfinite_input_rejected(orc):
 
 
 # ---------------------------------------------------------------------------------------------
-# The 10-D near-hover quadrotor of Sec. V, by subsystem
+# The 10-D near-hover quadrotor of Sec. VI, by subsystem
 # ---------------------------------------------------------------------------------------------
 
 def test_quad10_vertical_closed_form(orc):
