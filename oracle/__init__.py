@@ -88,6 +88,8 @@ def _load():
         lib.or_cfl_dt.restype = C.c_double
         lib.or_step.argtypes = [P(_Grid), P(_Dyn), P(_Opts), dp, dp, C.c_double, dp, dp]
         lib.or_solve.argtypes = [P(_Grid), P(_Dyn), dp, dp, P(_Opts), dp, P(_Result)]
+        lib.or_step_ra.argtypes = [P(_Grid), P(_Dyn), P(_Opts), dp, dp, dp, C.c_double, dp, dp]
+        lib.or_solve_ra.argtypes = [P(_Grid), P(_Dyn), dp, dp, dp, P(_Opts), dp, P(_Result)]
         lib.or_threads.restype = C.c_int
         lib.or_num_controls.argtypes = [C.c_int]
         lib.or_num_controls.restype = C.c_int
@@ -219,27 +221,31 @@ def cfl_dt(grid, dyn, cfl=0.8, dt_max=0.0) -> float:
     return float(dt)
 
 
-def step(grid, dyn, V, l, dt, **opts):
-    """One full time step: returns (V_next, max |V_next - V|)."""
+def step(grid, dyn, V, l, dt, constraint=None, **opts):
+    """One full time step: returns (V_next, max |V_next - V|).  constraint: the reach-avoid
+    constraint function g (the step then ends with max(g, .))."""
     V, l = _f64(V), _f64(l)
+    gc = None if constraint is None else _f64(constraint, V.shape)
     out = np.empty_like(V)
     delta = C.c_double()
     o = _opts(**opts)
-    if _load().or_step(C.byref(_grid(grid)), C.byref(_dyn(dyn)), C.byref(o), _ptr(l), _ptr(V), dt, _ptr(out),
-                       C.byref(delta)):
+    if _load().or_step_ra(C.byref(_grid(grid)), C.byref(_dyn(dyn)), C.byref(o), _ptr(l),
+                          None if gc is None else _ptr(gc), _ptr(V), dt, _ptr(out), C.byref(delta)):
         raise ValueError("or_step failed")
     return out, delta.value
 
 
-def solve(grid, dyn, l, k=None, **opts):
-    """Iterate to convergence from l (k is None) or from min(k, l).  Returns (V, info dict)."""
+def solve(grid, dyn, l, k=None, constraint=None, **opts):
+    """Iterate to convergence from l (k is None) or from min(k, l); with a reach-avoid
+    constraint function g, from max(g, .) with max(g, .) after every step.  Returns (V, info)."""
     l = _f64(l, grid.shape)
     kk = None if k is None else _f64(k, grid.shape)
+    gc = None if constraint is None else _f64(constraint, grid.shape)
     V = np.empty(grid.shape)
     res = _Result()
     o = _opts(**opts)
-    rc = _load().or_solve(C.byref(_grid(grid)), C.byref(_dyn(dyn)), _ptr(l), None if kk is None else _ptr(kk),
-                          C.byref(o), _ptr(V), C.byref(res))
+    rc = _load().or_solve_ra(C.byref(_grid(grid)), C.byref(_dyn(dyn)), _ptr(l), None if gc is None else _ptr(gc),
+                             None if kk is None else _ptr(kk), C.byref(o), _ptr(V), C.byref(res))
     if rc == -3:
         raise FloatingPointError("non-finite input")
     if rc:

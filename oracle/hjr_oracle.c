@@ -510,17 +510,19 @@ double or_cfl_dt(const or_grid *g, const or_dyn *dyn, double cfl, double dt_max)
  * it is never applied.  With a discount factor gamma in (0, 1) (discounted reachability,
  * Sec. II-C: the value one step later enters the dynamic programming principle multiplied by the
  * per-step factor, the target term not) the value of the full step is multiplied by gamma before
- * the projection. */
+ * the projection.  With a constraint function gc (reach-avoid: the state must also stay where
+ * gc <= 0) the full step ends with max(gc, .) after the projection. */
 static double stage_value(const or_grid *g, const or_dyn *dyn, const or_opts *o, int stage,
                           double dt, const double *Vs, const double *Vn, const double *l,
-                          int64_t i)
+                          const double *gc, int64_t i)
 {
     double L = lf_at(g, dyn, o->game, o->spatial, Vs, i);
     double gamma = (o->discount > 0.0 && o->discount < 1.0) ? o->discount : 1.0;
     double v;
     if (o->temporal == OR_EULER) {
         v = gamma * (Vs[i] + dt * L);
-        return (!o->brs && l[i] < v) ? l[i] : v;
+        if (!o->brs && l[i] < v) v = l[i];
+        return (gc && gc[i] > v) ? gc[i] : v;
     }
     if (stage == 1) {
         v = Vs[i] + dt * L;
@@ -533,7 +535,8 @@ static double stage_value(const or_grid *g, const or_dyn *dyn, const or_opts *o,
         return v;
     }
     v = gamma * (Vn[i] / 3.0 + 2.0 / 3.0 * (Vs[i] + dt * L));
-    return (!o->brs && l[i] < v) ? l[i] : v;
+    if (!o->brs && l[i] < v) v = l[i];
+    return (gc && gc[i] > v) ? gc[i] : v;
 }
 
 static int opts_ok(const or_opts *o)
@@ -556,19 +559,20 @@ int or_stage_at(const or_grid *g, const or_dyn *dyn, const or_opts *o, int stage
         if (nodes[c] < 0 || nodes[c] >= N) return -1;
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < count; ++c)
-        out[c] = stage_value(g, dyn, o, stage, dt, Vs, Vn, l, nodes[c]);
+        out[c] = stage_value(g, dyn, o, stage, dt, Vs, Vn, l, NULL, nodes[c]);
     return 0;
 }
 
-/* One full time step V -> Vout = min(l, step(V)), and delta = max_x |Vout - V|. */
-int or_step(const or_grid *g, const or_dyn *dyn, const or_opts *o, const double *l,
-            const double *V, double dt, double *Vout, double *delta)
+/* One full time step V -> Vout = min(l, step(V)) (then max(gc, .) when gc is given), and
+ * delta = max_x |Vout - V|. */
+int or_step_ra(const or_grid *g, const or_dyn *dyn, const or_opts *o, const double *l,
+               const double *gc, const double *V, double dt, double *Vout, double *delta)
 {
     if (!problem_ok(g, dyn, o ? o->spatial : 0) || !opts_ok(o)) return -1;
     int64_t N = grid_points(g);
     if (o->temporal == OR_EULER) {
 #pragma omp parallel for schedule(static)
-        for (int64_t i = 0; i < N; ++i) Vout[i] = stage_value(g, dyn, o, 1, dt, V, V, l, i);
+        for (int64_t i = 0; i < N; ++i) Vout[i] = stage_value(g, dyn, o, 1, dt, V, V, l, gc, i);
     } else {
         double *V1 = (double *)malloc(sizeof(double) * (size_t)N);
         double *V2 = (double *)malloc(sizeof(double) * (size_t)N);
@@ -578,11 +582,11 @@ int or_step(const or_grid *g, const or_dyn *dyn, const or_opts *o, const double 
             return -2;
         }
 #pragma omp parallel for schedule(static)
-        for (int64_t i = 0; i < N; ++i) V1[i] = stage_value(g, dyn, o, 1, dt, V, V, l, i);
+        for (int64_t i = 0; i < N; ++i) V1[i] = stage_value(g, dyn, o, 1, dt, V, V, l, gc, i);
 #pragma omp parallel for schedule(static)
-        for (int64_t i = 0; i < N; ++i) V2[i] = stage_value(g, dyn, o, 2, dt, V1, V, l, i);
+        for (int64_t i = 0; i < N; ++i) V2[i] = stage_value(g, dyn, o, 2, dt, V1, V, l, gc, i);
 #pragma omp parallel for schedule(static)
-        for (int64_t i = 0; i < N; ++i) Vout[i] = stage_value(g, dyn, o, 3, dt, V2, V, l, i);
+        for (int64_t i = 0; i < N; ++i) Vout[i] = stage_value(g, dyn, o, 3, dt, V2, V, l, gc, i);
         free(V1);
         free(V2);
     }
@@ -596,6 +600,12 @@ int or_step(const or_grid *g, const or_dyn *dyn, const or_opts *o, const double 
     return 0;
 }
 
+int or_step(const or_grid *g, const or_dyn *dyn, const or_opts *o, const double *l,
+            const double *V, double dt, double *Vout, double *delta)
+{
+    return or_step_ra(g, dyn, o, l, NULL, V, dt, Vout, delta);
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* Solve: march the variational inequality backwards in time until V stops changing           */
 /* ------------------------------------------------------------------------------------------ */
@@ -607,9 +617,12 @@ int or_step(const or_grid *g, const or_dyn *dyn, const or_opts *o, const double 
  * stops when the largest change of V across one whole interval is below tol.  Both modes also
  * stop at max_iter steps or when t reaches t_max (t_max > 0).  Discounted reachability (a
  * discount in (0, 1)) runs the same loop with the discounted step; the first time the test
- * passes, the discount is set to 1 (annealed) and the loop goes on instead of stopping. */
-int or_solve(const or_grid *g, const or_dyn *dyn, const double *l, const double *k,
-             const or_opts *o, double *V, or_result *res)
+ * passes, the discount is set to 1 (annealed) and the loop goes on instead of stopping.
+ * Reach-avoid (gc given): V0 = max(gc, l) or max(gc, min(k, l)), and every step ends with
+ * max(gc, .); the set {V <= 0} is then the set of states that can reach {l <= 0} while keeping
+ * gc <= 0 on the way. */
+int or_solve_ra(const or_grid *g, const or_dyn *dyn, const double *l, const double *gc,
+                const double *k, const or_opts *o, double *V, or_result *res)
 {
     if (!problem_ok(g, dyn, o ? o->spatial : 0) || !opts_ok(o) || !(o->cfl > 0.0) ||
         !(o->tol > 0.0) || !res)
@@ -620,8 +633,9 @@ int or_solve(const or_grid *g, const or_dyn *dyn, const double *l, const double 
     int64_t disc_steps = 0;
     int64_t N = grid_points(g);
     for (int64_t i = 0; i < N; ++i) {
-        if (!isfinite(l[i]) || (k && !isfinite(k[i]))) return -3;
+        if (!isfinite(l[i]) || (k && !isfinite(k[i])) || (gc && !isfinite(gc[i]))) return -3;
         V[i] = (k && k[i] < l[i]) ? k[i] : l[i];
+        if (gc && gc[i] > V[i]) V[i] = gc[i];
     }
     double *Vnext = (double *)malloc(sizeof(double) * (size_t)N);
     double *Vstart = o->conv_mode == OR_CONV_INTERVAL ? (double *)malloc(sizeof(double) * (size_t)N) : NULL;
@@ -646,7 +660,7 @@ int or_solve(const or_grid *g, const or_dyn *dyn, const double *l, const double 
         if (o->t_max > 0.0 && o->t_max - t < dt) dt = o->t_max - t;
         if (o->conv_mode == OR_CONV_INTERVAL && o->dt_report - t_int < dt) dt = o->dt_report - t_int;
         double delta;
-        or_step(g, dyn, &cur, l, V, dt, Vnext, &delta);
+        or_step_ra(g, dyn, &cur, l, gc, V, dt, Vnext, &delta);
         memcpy(V, Vnext, sizeof(double) * (size_t)N);
         steps += 1;
         t += dt;
@@ -697,6 +711,12 @@ int or_solve(const or_grid *g, const or_dyn *dyn, const double *l, const double 
     free(Vnext);
     free(Vstart);
     return 0;
+}
+
+int or_solve(const or_grid *g, const or_dyn *dyn, const double *l, const double *k,
+             const or_opts *o, double *V, or_result *res)
+{
+    return or_solve_ra(g, dyn, l, NULL, k, o, V, res);
 }
 
 /* ------------------------------------------------------------------------------------------ */

@@ -108,6 +108,12 @@ int or_step(const or_grid *g, const or_dyn *dyn, const or_opts *o, const double 
             const double *V, double dt, double *Vout, double *delta);
 int or_solve(const or_grid *g, const or_dyn *dyn, const double *l, const double *k,
              const or_opts *o, double *V, or_result *res);
+/* Reach-avoid variants: gc is a constraint function (the state must keep gc <= 0); each step
+ * ends with max(gc, min(l, V_step)) and the start is max(gc, min(k, l)).  gc NULL: as above. */
+int or_step_ra(const or_grid *g, const or_dyn *dyn, const or_opts *o, const double *l,
+               const double *gc, const double *V, double dt, double *Vout, double *delta);
+int or_solve_ra(const or_grid *g, const or_dyn *dyn, const double *l, const double *gc,
+                const double *k, const or_opts *o, double *V, or_result *res);
 int or_threads(void);
 
 /* Safe control (Sec. II-B.2, eq. (uOpt)).  or_num_controls: number of control inputs of a model

@@ -628,3 +628,94 @@ def test_discount_forgets_a_stuck_initialization(orc):
     assert ic["discounted_steps"] > 0 and ik["discounted_steps"] > 0
     assert np.abs(Vc - Vk).max() <= 3 * o["tol"] / (1 - gamma)
     assert np.abs(Vs - Vc).max() > 0.5  # the undiscounted stuck start does not get there
+
+
+# ---------------------------------------------------------------------------------------------
+# Reach-avoid (the problem class named in Sec. II): V <- max(g, min(l, V_step)), V0 = max(g, l)
+# ---------------------------------------------------------------------------------------------
+
+def _reach_avoid_di(n):
+    """Double integrator, reach game: target box |x_i| <= 0.2, constraint g > 0 inside a slab
+    left of it and inside a small box over the target's corner (so target and obstacle meet)."""
+    pr = W.di_box_problem(n, ubar=1.0, dbar=0.2)
+    gc = np.maximum(-W.box_sdf(pr.grid, (-0.5, 0.0), (0.1, 0.6)), -W.box_sdf(pr.grid, (0.2, 0.2), (0.08, 0.08)))
+    return pr, gc
+
+
+def test_reach_avoid_zero_flow_closed_form(orc):
+    """Without motion the step is the identity, so the solve stops after one step at
+    max(g, min(k, l)); where g > 0 and l < 0 the obstacle wins."""
+    g = W.Grid((9, 10, 8), (-1.0, -1.0, -math.pi), (1.0, 1.0, math.pi), (False, False, True))
+    dyn = W.dubins3(0.0, 0.0, 0.0, 0.0)
+    l, gc, k = W.smooth_field(g, seed=2), W.smooth_field(g, seed=3), W.smooth_field(g, seed=4)
+    assert ((gc > 0) & (l < 0)).any()
+    for kk in (None, k):
+        for temporal in (orc.EULER, orc.RK3):
+            V, info = orc.solve(g, dyn, l, kk, constraint=gc, spatial=orc.UPWIND1, temporal=temporal, game=REACH)
+            assert info["steps"] == 1 and info["converged"] == 1
+            start = l if kk is None else np.minimum(kk, l)
+            assert np.abs(V - np.maximum(gc, start)).max() <= 1e-15
+
+
+def test_reach_avoid_with_an_idle_constraint_is_plain_reach(orc):
+    pr, _ = _reach_avoid_di(31)
+    o = dict(spatial=orc.UPWIND1, temporal=orc.EULER, cfl=0.8, tol=1e-8, game=REACH)
+    Vr, ir = orc.solve(pr.grid, pr.dyn, pr.l, **o)
+    Va, ia = orc.solve(pr.grid, pr.dyn, pr.l, constraint=np.full(pr.l.shape, -1e3), **o)
+    assert np.array_equal(Vr, Va) and ir["steps"] == ia["steps"]
+
+
+def test_reach_avoid_iterates_lie_above_reach_iterates(orc):
+    """Comparison principle for the monotone scheme (no boundary): the reach-avoid iterate starts
+    above the reach iterate and max(g, .) only raises it, so it stays above at every step, and
+    above g; the constraint shrinks the reach set."""
+    g, dyn, l = _periodic_di(n=31)
+    gc = -W.box_sdf(g, (-0.5, 0.0), (0.1, 0.6))
+    dt = orc.cfl_dt(g, dyn, 0.8)
+    Vr, Va = l.copy(), np.maximum(gc, l)
+    for _ in range(200):
+        Vr, _ = orc.step(g, dyn, Vr, l, dt, spatial=orc.UPWIND1, temporal=orc.EULER, game=REACH)
+        Va, _ = orc.step(g, dyn, Va, l, dt, constraint=gc, spatial=orc.UPWIND1, temporal=orc.EULER, game=REACH)
+        assert (Va >= Vr - 1e-13).all() and (Va >= gc).all()
+    assert ((Vr <= 0) & (Va > 0)).sum() > 20
+
+
+def _semi_lagrangian_reach_avoid(g, ubar, b, dbar, l, gc, h=0.02, k=11, iters=5000):
+    """V(x) = max(g(x), min(l(x), min_u max_d V(x + h f(x,u,d)))) on the grid (the reach-avoid
+    dynamic programming principle with one Euler step of the trajectory), iterated to a fixed
+    point."""
+    ax = (g.axis(0), g.axis(1))
+    X1, X2 = np.meshgrid(*ax, indexing="ij")
+    us, ds = np.linspace(-ubar, ubar, k), np.linspace(-dbar, dbar, k)
+    V = np.maximum(gc, l)
+    for _ in range(iters):
+        f = RegularGridInterpolator(ax, V, bounds_error=False, fill_value=None)
+        best = np.full(V.shape, np.inf)
+        for u in us:
+            worst = np.full(V.shape, -np.inf)
+            for d in ds:
+                y = np.stack([(X1 + h * (X2 + d)).ravel(), (X2 + h * b * u).ravel()], -1)
+                worst = np.maximum(worst, f(y).reshape(V.shape))
+            best = np.minimum(best, worst)
+        Vn = np.maximum(gc, np.minimum(l, best))
+        if np.abs(Vn - V).max() < 1e-10:
+            return Vn
+        V = Vn
+    return V
+
+
+def test_reach_avoid_brute_force_dynamic_programming(orc):
+    """Compared away from the domain edge: at the corners, where the extrapolated edge values let
+    characteristics enter, the first-order scheme keeps a small limit cycle (so a fixed number of
+    steps, long after the interior has settled)."""
+    pr, gc = _reach_avoid_di(31)
+    Vo, _ = orc.solve(pr.grid, pr.dyn, pr.l, constraint=gc, spatial=orc.UPWIND1, temporal=orc.EULER,
+                      cfl=0.8, tol=1e-9, game=REACH, max_iter=3000)
+    Vs = _semi_lagrangian_reach_avoid(pr.grid, 1.0, 1.0, 0.2, pr.l, gc, iters=1000)
+    X1, X2 = np.meshgrid(pr.grid.axis(0), pr.grid.axis(1), indexing="ij")
+    m = (np.abs(X1) <= 0.8) & (np.abs(X2) <= 0.8)
+    err = np.abs(Vo - Vs)[m]
+    assert np.abs(Vo - np.maximum(gc, pr.l)).max() > 0.5  # the solve moved V
+    assert err.max() < 0.04 and err.mean() < 2e-3
+    assert ((Vo <= 0) != (Vs <= 0))[m].sum() <= 2
+    assert ((gc > 0) & (pr.l < 0) & (Vo > 0)).any()  # where the obstacle covers the target it wins
