@@ -198,6 +198,22 @@ hjr_status hjr_solve_device(const hjr_grid *grid, const hjr_dynamics *dyn, const
                             const double *k_dev, const hjr_options *opts, double *V_dev,
                             void *stream, hjr_result *result);
 
+/* Reach-avoid solve (the reach-avoid problems that Sec. II names beside reach and avoid): a
+ * constraint function g (prod(n) doubles, finite, same layout as l) marks where the state may
+ * not go (g > 0).  Every step ends with V <- max(g, min(l, V_step)) and the start is
+ * max(g, l), or max(g, min(k, l)) with a warm start.  With HJR_REACH, {V <= 0} is the set of
+ * states that can reach {l <= 0} while keeping g <= 0 on the way, whatever the disturbance.
+ * Every option applies as in hjr_solve except brs (refused).  The library keeps an FP32 copy of
+ * g in FP32 phases (4 more bytes per node).  g NULL is HJR_ERR_INVALID_ARG.  The device variant
+ * takes device arrays on `stream` as hjr_solve_device does. */
+hjr_status hjr_solve_reach_avoid(const hjr_grid *grid, const hjr_dynamics *dyn, const double *l,
+                                 const double *g, const double *k, const hjr_options *opts,
+                                 double *V_out, hjr_result *result);
+hjr_status hjr_solve_reach_avoid_device(const hjr_grid *grid, const hjr_dynamics *dyn,
+                                        const double *l_dev, const double *g_dev,
+                                        const double *k_dev, const hjr_options *opts,
+                                        double *V_dev, void *stream, hjr_result *result);
+
 /* Batched solve: `count` independent problems (host arrays) advanced together, every stage of
  * every instance in one launch per stage.  Each problem's status and result are filled in; the
  * return value is HJR_OK if every problem converged, else the first non-OK status. */

@@ -279,6 +279,7 @@ struct Request {
     hjr_options opts;
     const double *l_dev = nullptr;   // FP64 target function (caller or owned)
     const double *k_dev = nullptr;
+    const double *g_dev = nullptr;   // reach-avoid constraint function (caller or owned), or null
     double *V_dev = nullptr;         // FP64 output (caller or owned)
     uint64_t npts = 0;
     size_t bytes = 0;                // working memory
@@ -347,11 +348,11 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Working memory of one request, carved from one pool block.
 struct Layout {
-    size_t V32, A32, B32, l32, Vs32, A64, B64, Vs64, V64, l64, k64, tab32, tab64, total;
+    size_t V32, A32, B32, l32, g32, Vs32, A64, B64, Vs64, V64, l64, k64, g64, tab32, tab64, total;
     int ntab;
 };
 
-static Layout plan_layout(const Request &r, bool own_io)
+static Layout plan_layout(const Request &r, bool own_io, bool has_g)
 {
     Layout L{};
     const size_t N = r.npts;
@@ -365,6 +366,7 @@ static Layout plan_layout(const Request &r, bool own_io)
     L.A32 = fp32 ? take(N * 4) : none;
     L.B32 = fp32 && r.opts.temporal == HJR_TVDRK3 ? take(N * 4) : none;
     L.l32 = fp32 ? take(N * 4) : none;
+    L.g32 = fp32 && has_g ? take(N * 4) : none;
     L.Vs32 = fp32 && interval ? take(N * 4) : none;
     L.A64 = fp64 ? take(N * 8) : none;
     L.B64 = fp64 && r.opts.temporal == HJR_TVDRK3 ? take(N * 8) : none;
@@ -372,6 +374,7 @@ static Layout plan_layout(const Request &r, bool own_io)
     L.V64 = own_io ? take(N * 8) : none;
     L.l64 = own_io ? take(N * 8) : none;
     L.k64 = own_io ? take(N * 8) : none;
+    L.g64 = own_io && has_g ? take(N * 8) : none;
     int nt = 0;
     for (int d = 0; d < r.grid.ndim; ++d) nt += r.grid.n[d];
     nt += 2 * r.grid.n[std::min(2, r.grid.ndim - 1)];
@@ -382,7 +385,7 @@ static Layout plan_layout(const Request &r, bool own_io)
     return L;
 }
 
-static size_t request_bytes(const Request &r, bool own_io) { return plan_layout(r, own_io).total; }
+static size_t request_bytes(const Request &r, bool own_io) { return plan_layout(r, own_io, r.g_dev != nullptr).total; }
 
 // Grid part of an instance descriptor: sizes, strides, division constants, spacings.
 static void fill_grid(const hjr_grid &g, uint64_t npts, Inst &I)
@@ -460,12 +463,14 @@ static void build_inst(Request &r, char *base, const Layout &L, std::vector<doub
     I.A32 = (float *)at(L.A32);
     I.B32 = (float *)at(L.B32);
     I.l32 = (const float *)at(L.l32);
+    I.g32 = (const float *)at(L.g32);
     I.Vs32 = (float *)at(L.Vs32);
     I.A64 = (double *)at(L.A64);
     I.B64 = (double *)at(L.B64);
     I.Vs64 = (double *)at(L.Vs64);
     I.V64 = r.V_dev;
     I.l64 = r.l_dev;
+    I.g64 = r.g_dev;
     I.state = state_dev;
 }
 
@@ -494,11 +499,15 @@ static SolveState initial_state(const Request &r)
 // The per-node arithmetic is identical for every candidate (results are bitwise equal), so the
 // tuner explores on the real solve: successive chunks of steps run with successive candidates,
 // the median duration of each candidate's stage launches is recorded, and once every candidate
-// has been timed the fastest is used from then on, for the rest of the process.  With
+// has been timed the fastest is used from then on, for the rest of the process.  The default is
+// timed first and again last (its best time counts), so a clock that is still rising during the
+// first chunks does not count against it.  With
 // HJR_TUNE_CACHE=<file> the choices are also kept in a small JSON file for later processes.
 // --------------------------------------------------------------------------------------------
 
 static const int kNptCandidates[] = {4, 2, 8, 1};
+static const int kNptSchedule[] = {4, 2, 8, 1, 4};
+static const int kNptScheduleLen = (int)(sizeof kNptSchedule / sizeof kNptSchedule[0]);
 
 class Tuner {
 public:
@@ -527,16 +536,15 @@ public:
     int next_candidate(const std::string &k)
     {
         std::lock_guard<std::mutex> g(mu_);
-        auto &m = timed_[k];
-        for (int c : kNptCandidates)
-            if (!m.count(c)) return c;
-        return kNptCandidates[0];
+        const int n = count_[k];
+        return n < kNptScheduleLen ? kNptSchedule[n] : kNptCandidates[0];
     }
     void record(const std::string &k, int npt, double us)
     {
         std::lock_guard<std::mutex> g(mu_);
         auto &m = timed_[k];
         m[npt] = m.count(npt) ? std::min(m[npt], us) : us;
+        if (++count_[k] < kNptScheduleLen) return;
         for (int c : kNptCandidates)
             if (!m.count(c)) return;
         // another candidate must beat the default by 8% (and the best so far by 2%): near-ties
@@ -583,6 +591,7 @@ private:
     std::mutex mu_;
     std::map<std::string, int> chosen_;
     std::map<std::string, std::map<int, double>> timed_;
+    std::map<std::string, int> count_;  // timings recorded per key
     bool loaded_ = false;
 };
 
@@ -675,7 +684,8 @@ public:
 
     // Start a request: allocate, upload descriptors and tables, launch init + setup.
     // own_io: the library owns l/k/V device copies (host-pointer path); host arrays given.
-    hjr_status admit(Request *r, bool own_io, const double *l_host, const double *k_host)
+    hjr_status admit(Request *r, bool own_io, const double *l_host, const double *k_host,
+                     const double *g_host = nullptr)
     {
         int slot = -1;
         for (int i = 0; i < cap_; ++i)
@@ -684,7 +694,7 @@ public:
                 break;
             }
         if (slot < 0) return fail(HJR_ERR_INVALID_ARG, "engine is full");
-        Layout L = plan_layout(*r, own_io);
+        Layout L = plan_layout(*r, own_io, own_io ? g_host != nullptr : r->g_dev != nullptr);
         r->bytes = L.total;
         HJR_HIP(Pool::get().alloc(&r->mem, L.total));
         char *base = (char *)r->mem;
@@ -695,6 +705,9 @@ public:
             HJR_HIP(hipMemcpyAsync((void *)r->l_dev, l_host, r->npts * 8, hipMemcpyHostToDevice, stream_));
             if (k_host)
                 HJR_HIP(hipMemcpyAsync((void *)r->k_dev, k_host, r->npts * 8, hipMemcpyHostToDevice, stream_));
+            r->g_dev = g_host ? (const double *)(base + L.g64) : nullptr;
+            if (g_host)
+                HJR_HIP(hipMemcpyAsync((void *)r->g_dev, g_host, r->npts * 8, hipMemcpyHostToDevice, stream_));
         }
         std::vector<double> t64;
         std::vector<float> t32;
@@ -1205,7 +1218,8 @@ static hjr_status prepare(Request &r, const hjr_grid *g, const hjr_dynamics *dy,
 
 // Run a set of requests to completion on one engine (used by the synchronous entry points).
 static hjr_status run_all(Engine &E, std::vector<Request *> &reqs, bool own_io, const std::vector<const double *> &lh,
-                          const std::vector<const double *> &kh, int steps_per_sync)
+                          const std::vector<const double *> &kh, int steps_per_sync,
+                          const double *g_host = nullptr)
 {
     size_t next = 0;
     ChunkPolicy pol(steps_per_sync);
@@ -1213,7 +1227,8 @@ static hjr_status run_all(Engine &E, std::vector<Request *> &reqs, bool own_io, 
     while (next < reqs.size() || E.active() > 0) {
         while (next < reqs.size() && E.has_free_slot()) {
             Request *r = reqs[next];
-            hjr_status s = E.admit(r, own_io, own_io ? lh[next] : nullptr, own_io ? kh[next] : nullptr);
+            hjr_status s = E.admit(r, own_io, own_io ? lh[next] : nullptr, own_io ? kh[next] : nullptr,
+                                   own_io && next == 0 ? g_host : nullptr);
             if (s != HJR_OK) return s;
             ++next;
         }
@@ -1295,18 +1310,19 @@ int32_t hjr_device_count(void)
     return n;
 }
 
-hjr_status hjr_solve(const hjr_grid *grid, const hjr_dynamics *dyn, const double *l, const double *k,
-                     const hjr_options *opts, double *V_out, hjr_result *result)
+static hjr_status solve_host(const hjr_grid *grid, const hjr_dynamics *dyn, const double *l, const double *g,
+                             const double *k, const hjr_options *opts, double *V_out, hjr_result *result)
 {
     Request r;
     hjr_status s = prepare(r, grid, dyn, opts, k);
     if (s != HJR_OK) return s;
     if (!l || !V_out) return fail(HJR_ERR_INVALID_ARG, "l and V_out must not be NULL");
+    if (g && opts->brs) return fail(HJR_ERR_INVALID_ARG, "the reachable-set mode takes no constraint function");
     Engine E(1);
     s = E.init(nullptr);
     if (s != HJR_OK) return s;
     std::vector<Request *> reqs{&r};
-    s = run_all(E, reqs, true, {l}, {k}, opts->steps_per_sync);
+    s = run_all(E, reqs, true, {l}, {k}, opts->steps_per_sync, g);
     if (s == HJR_OK && r.status >= 0) {
         hipError_t e = hipMemcpy(V_out, r.V_dev, r.npts * 8, hipMemcpyDeviceToHost);
         if (e != hipSuccess) s = fail(HJR_ERR_DEVICE, "copy of V failed: %s", hipGetErrorString(e));
@@ -1317,15 +1333,18 @@ hjr_status hjr_solve(const hjr_grid *grid, const hjr_dynamics *dyn, const double
     return r.status;
 }
 
-hjr_status hjr_solve_device(const hjr_grid *grid, const hjr_dynamics *dyn, const double *l_dev, const double *k_dev,
-                            const hjr_options *opts, double *V_dev, void *stream, hjr_result *result)
+static hjr_status solve_dev(const hjr_grid *grid, const hjr_dynamics *dyn, const double *l_dev, const double *g_dev,
+                            const double *k_dev, const hjr_options *opts, double *V_dev, void *stream,
+                            hjr_result *result)
 {
     Request r;
     hjr_status s = prepare(r, grid, dyn, opts, k_dev);
     if (s != HJR_OK) return s;
     if (!l_dev || !V_dev) return fail(HJR_ERR_INVALID_ARG, "l_dev and V_dev must not be NULL");
+    if (g_dev && opts->brs) return fail(HJR_ERR_INVALID_ARG, "the reachable-set mode takes no constraint function");
     r.l_dev = l_dev;
     r.k_dev = k_dev;
+    r.g_dev = g_dev;
     r.V_dev = V_dev;
     Engine E(1);
     s = E.init((hipStream_t)stream);
@@ -1336,6 +1355,33 @@ hjr_status hjr_solve_device(const hjr_grid *grid, const hjr_dynamics *dyn, const
     if (s != HJR_OK) return s;
     if (result) *result = r.result;
     return r.status;
+}
+
+hjr_status hjr_solve(const hjr_grid *grid, const hjr_dynamics *dyn, const double *l, const double *k,
+                     const hjr_options *opts, double *V_out, hjr_result *result)
+{
+    return solve_host(grid, dyn, l, nullptr, k, opts, V_out, result);
+}
+
+hjr_status hjr_solve_device(const hjr_grid *grid, const hjr_dynamics *dyn, const double *l_dev, const double *k_dev,
+                            const hjr_options *opts, double *V_dev, void *stream, hjr_result *result)
+{
+    return solve_dev(grid, dyn, l_dev, nullptr, k_dev, opts, V_dev, stream, result);
+}
+
+hjr_status hjr_solve_reach_avoid(const hjr_grid *grid, const hjr_dynamics *dyn, const double *l, const double *g,
+                                 const double *k, const hjr_options *opts, double *V_out, hjr_result *result)
+{
+    if (!g) return fail(HJR_ERR_INVALID_ARG, "g must not be NULL");
+    return solve_host(grid, dyn, l, g, k, opts, V_out, result);
+}
+
+hjr_status hjr_solve_reach_avoid_device(const hjr_grid *grid, const hjr_dynamics *dyn, const double *l_dev,
+                                        const double *g_dev, const double *k_dev, const hjr_options *opts,
+                                        double *V_dev, void *stream, hjr_result *result)
+{
+    if (!g_dev) return fail(HJR_ERR_INVALID_ARG, "g_dev must not be NULL");
+    return solve_dev(grid, dyn, l_dev, g_dev, k_dev, opts, V_dev, stream, result);
 }
 
 hjr_status hjr_batch_solve(int32_t count, hjr_problem *problems)
@@ -1454,7 +1500,7 @@ hjr_status hjr_stage_device(const hjr_grid *grid, const hjr_dynamics *dyn, int32
     const bool f32 = precision == HJR_FP32;
     const size_t esz = f32 ? 4 : 8;
     // descriptor with the caller's arrays in the roles the kernel expects for this stage
-    Layout L = plan_layout(r, false);
+    Layout L = plan_layout(r, false, false);
     void *mem = nullptr;
     HJR_HIP(Pool::get().alloc(&mem, L.total + align256(sizeof(SolveState)) + align256(sizeof(Inst))));
     char *base = (char *)mem;

@@ -109,6 +109,8 @@ struct Inst {
     const float *l32;
     double *V64, *A64, *B64;
     const double *l64;
+    const float *g32;        // reach-avoid constraint function (nullptr: none)
+    const double *g64;
     float *Vs32;             // interval-mode snapshot (FP32 phase)
     double *Vs64;            // interval-mode snapshot (FP64 phase)
     SolveState *state;
@@ -128,6 +130,7 @@ template <> struct Fields<float> {
     __device__ static float *A(const Inst &I) { return I.A32; }
     __device__ static float *B(const Inst &I) { return I.B32; }
     __device__ static const float *l(const Inst &I) { return I.l32; }
+    __device__ static const float *g(const Inst &I) { return I.g32; }
     __device__ static float *snap(const Inst &I) { return I.Vs32; }
     __device__ static float hinv_dx(const Inst &I, int d) { return I.hinv_dx32[d]; }
     __device__ static float eps0(const Inst &I, int d) { return I.eps0_32[d]; }
@@ -139,6 +142,7 @@ template <> struct Fields<double> {
     __device__ static double *A(const Inst &I) { return I.A64; }
     __device__ static double *B(const Inst &I) { return I.B64; }
     __device__ static const double *l(const Inst &I) { return I.l64; }
+    __device__ static const double *g(const Inst &I) { return I.g64; }
     __device__ static double *snap(const Inst &I) { return I.Vs64; }
     __device__ static double hinv_dx(const Inst &I, int d) { return I.hinv_dx64[d]; }
     __device__ static double eps0(const Inst &I, int d) { return I.eps0_64[d]; }

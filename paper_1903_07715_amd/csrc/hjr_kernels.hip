@@ -125,6 +125,7 @@ __device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int st
     Vn = uniform_ptr(Vn);
     O = uniform_ptr(O);
     const T *l = uniform_ptr(F::l(I));
+    const T *G = uniform_ptr(F::g(I));  // reach-avoid constraint, or nullptr
     const T gm = (T)st->gamma;  // discount (1 outside discounted reachability: x * 1 == x exactly)
     T delta = T(0);  // in the field's precision: the max of exact differences is exact
     // NPT nodes per thread, kBlock apart: independent work the scheduler can interleave
@@ -136,6 +137,7 @@ __device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int st
         if (euler) {
             out = gm * (s + dt * L);
             if (!I.brs) out = fmin(ldg(l, node), out);
+            if (G) out = fmax(ldg(G, node), out);
         } else if (stage == 0) {
             out = s + dt * L;
         } else if (stage == 1) {
@@ -143,6 +145,7 @@ __device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int st
         } else {
             out = gm * (vn * T(1.0 / 3.0) + T(2.0 / 3.0) * (s + dt * L));
             if (!I.brs) out = fmin(ldg(l, node), out);
+            if (G) out = fmax(ldg(G, node), out);
         }
         stg(O, node, out);
         if (last) delta = nanmax(delta, T(fabs(out - vn)));
@@ -363,6 +366,12 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const Inst *__restrict__ i
             bad |= isfinite(k) ? 0u : 1u;
             v = k < l ? k : l;
         }
+        if (I.g64) {  // reach-avoid: start from max(g, .)
+            const double gv = I.g64[node];
+            bad |= isfinite(gv) ? 0u : 1u;
+            v = gv > v ? gv : v;
+            if (fp32) const_cast<float *>(I.g32)[node] = (float)gv;
+        }
         lmax = fabs(l);
         if (fp32) {
             I.V32[node] = (float)v;
@@ -463,7 +472,8 @@ __global__ __launch_bounds__(kBlock) void polish_init_kernel(const Inst *__restr
     const double shift = I.state->tol32_req;
     const double l = I.l64[node];
     const double v = (double)cur[node] + shift;
-    const double v0 = v < l ? v : l;
+    double v0 = v < l ? v : l;
+    if (I.g64 && I.g64[node] > v0) v0 = I.g64[node];
     I.V64[node] = v0;
     if (I.Vs64) I.Vs64[node] = v0;
 }

@@ -30,7 +30,8 @@ EXPORTED = ["hjr_abi_version", "hjr_default_options", "hjr_status_string", "hjr_
             "hjr_device_count", "hjr_solve", "hjr_solve_device", "hjr_batch_solve", "hjr_cfl_dt",
             "hjr_stage_device", "hjr_ctx_create", "hjr_submit", "hjr_poll", "hjr_ctx_drain",
             "hjr_ctx_get_stats", "hjr_ctx_destroy", "hjr_profile_enable", "hjr_profile_read",
-            "hjr_num_controls", "hjr_gradient_device", "hjr_safe_control_device"]
+            "hjr_num_controls", "hjr_gradient_device", "hjr_safe_control_device", "hjr_solve_reach_avoid",
+            "hjr_solve_reach_avoid_device"]
 
 
 class Grid_(C.Structure):
@@ -113,6 +114,9 @@ def load():
         lib.hjr_num_controls.restype = C.c_int32
         lib.hjr_solve.argtypes = [P(Grid_), P(Dynamics_), dp, dp, P(Options_), dp, P(Result_)]
         lib.hjr_solve_device.argtypes = [P(Grid_), P(Dynamics_), vp, vp, P(Options_), vp, vp, P(Result_)]
+        lib.hjr_solve_reach_avoid.argtypes = [P(Grid_), P(Dynamics_), dp, dp, dp, P(Options_), dp, P(Result_)]
+        lib.hjr_solve_reach_avoid_device.argtypes = [P(Grid_), P(Dynamics_), vp, vp, vp, P(Options_), vp, vp,
+                                                     P(Result_)]
         lib.hjr_batch_solve.argtypes = [C.c_int32, P(Problem_)]
         lib.hjr_cfl_dt.argtypes = [P(Grid_), P(Dynamics_), C.c_double, C.c_double, dp]
         lib.hjr_stage_device.argtypes = [P(Grid_), P(Dynamics_), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
@@ -208,15 +212,22 @@ def device_count() -> int:
     return int(load().hjr_device_count())
 
 
-def solve(grid, dyn, l: np.ndarray, k: Optional[np.ndarray] = None, **opts):
-    """hjr_solve with host arrays.  Returns (V, result dict, status)."""
+def solve(grid, dyn, l: np.ndarray, k: Optional[np.ndarray] = None, constraint: Optional[np.ndarray] = None,
+          **opts):
+    """hjr_solve with host arrays (hjr_solve_reach_avoid when a constraint function g is given).
+    Returns (V, result dict, status)."""
     l = np.ascontiguousarray(l, dtype=np.float64).reshape(grid.shape)
     kk = None if k is None else np.ascontiguousarray(k, dtype=np.float64).reshape(grid.shape)
     V = np.empty(grid.shape, dtype=np.float64)
     res = Result_()
     o = options(**opts)
-    st = load().hjr_solve(C.byref(grid_struct(grid)), C.byref(dyn_struct(dyn)), _dptr(l),
-                          None if kk is None else _dptr(kk), C.byref(o), _dptr(V), C.byref(res))
+    gs, ds = C.byref(grid_struct(grid)), C.byref(dyn_struct(dyn))
+    kp = None if kk is None else _dptr(kk)
+    if constraint is None:
+        st = load().hjr_solve(gs, ds, _dptr(l), kp, C.byref(o), _dptr(V), C.byref(res))
+    else:
+        gc = np.ascontiguousarray(constraint, dtype=np.float64).reshape(grid.shape)
+        st = load().hjr_solve_reach_avoid(gs, ds, _dptr(l), _dptr(gc), kp, C.byref(o), _dptr(V), C.byref(res))
     _check(st)
     return V, result_dict(res), st
 
@@ -231,15 +242,21 @@ def _stream_ptr(stream) -> Optional[int]:
     return int(getattr(stream, "cuda_stream", stream))
 
 
-def solve_device(grid, dyn, l_dev, k_dev, V_dev, stream=None, **opts):
-    """hjr_solve_device on torch FP64 device tensors.  Returns (result dict, status)."""
-    for t in (l_dev, k_dev, V_dev):
+def solve_device(grid, dyn, l_dev, k_dev, V_dev, stream=None, constraint=None, **opts):
+    """hjr_solve_device on torch FP64 device tensors (hjr_solve_reach_avoid_device when a
+    constraint function g is given as a device tensor).  Returns (result dict, status)."""
+    for t in (l_dev, k_dev, V_dev, constraint):
         if t is not None and (not t.is_cuda or t.dtype.itemsize != 8 or not t.is_contiguous()):
             raise ValueError("device arrays must be contiguous FP64 GPU tensors")
     res = Result_()
     o = options(**opts)
-    st = load().hjr_solve_device(C.byref(grid_struct(grid)), C.byref(dyn_struct(dyn)), _tptr(l_dev), _tptr(k_dev),
-                                 C.byref(o), _tptr(V_dev), _stream_ptr(stream), C.byref(res))
+    gs, ds = C.byref(grid_struct(grid)), C.byref(dyn_struct(dyn))
+    if constraint is None:
+        st = load().hjr_solve_device(gs, ds, _tptr(l_dev), _tptr(k_dev), C.byref(o), _tptr(V_dev),
+                                     _stream_ptr(stream), C.byref(res))
+    else:
+        st = load().hjr_solve_reach_avoid_device(gs, ds, _tptr(l_dev), _tptr(constraint), _tptr(k_dev), C.byref(o),
+                                                 _tptr(V_dev), _stream_ptr(stream), C.byref(res))
     _check(st)
     return result_dict(res), st
 

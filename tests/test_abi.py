@@ -205,3 +205,26 @@ def test_discount_arguments():
         assert st == hjr.ERR_INVALID_ARG and "discount" in msg
     st, msg = _call_solve(g, d, brs=1, t_max=0.5, precision=hjr.FP64, discount=0.99)
     assert st == hjr.ERR_INVALID_ARG and "discount" in msg
+
+
+def test_reach_avoid_arguments():
+    """The reach-avoid entry points need a constraint array and refuse the reachable-set mode;
+    both are rejected before any device work."""
+    g = W.Grid((11, 11), (-1, -1), (1, 1))
+    d = W.double_integrator()
+    l = np.zeros(g.size)
+    V = np.zeros(g.size)
+    res = hjr.Result_()
+    dp = C.POINTER(C.c_double)
+    lib = hjr.load()
+    o = hjr.options()
+    st = lib.hjr_solve_reach_avoid(C.byref(hjr.grid_struct(g)), C.byref(hjr.dyn_struct(d)), l.ctypes.data_as(dp),
+                                   None, None, C.byref(o), V.ctypes.data_as(dp), C.byref(res))
+    assert st == hjr.ERR_INVALID_ARG and "g must not be NULL" in hjr.last_error()
+    o = hjr.options(brs=1, t_max=0.5, precision=hjr.FP64)
+    st = lib.hjr_solve_reach_avoid(C.byref(hjr.grid_struct(g)), C.byref(hjr.dyn_struct(d)), l.ctypes.data_as(dp),
+                                   l.ctypes.data_as(dp), None, C.byref(o), V.ctypes.data_as(dp), C.byref(res))
+    assert st == hjr.ERR_INVALID_ARG and "constraint" in hjr.last_error()
+    st = lib.hjr_solve_reach_avoid_device(C.byref(hjr.grid_struct(g)), C.byref(hjr.dyn_struct(d)), None, None, None,
+                                          C.byref(hjr.options()), None, None, C.byref(res))
+    assert st == hjr.ERR_INVALID_ARG

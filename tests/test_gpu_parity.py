@@ -316,3 +316,55 @@ def test_discounted_fp32_polish_and_batch(gpu, hjrlib, orc):
         assert st == sta == hjrlib.OK
         assert r["discounted_iterations"] == ra["discounted_iterations"]
         assert np.array_equal(V, Va)
+
+
+def _reach_avoid_periodic_di():
+    g, dyn, l = _periodic_di()
+    gc = np.maximum(-W.box_sdf(g, (-0.5, 0.0), (0.1, 0.6)), -W.box_sdf(g, (0.2, 0.2), (0.08, 0.08)))
+    return g, dyn, l, gc
+
+
+@pytest.mark.parametrize("warm", [False, True], ids=["cold", "warm"])
+def test_reach_avoid_matches_oracle(gpu, hjrlib, orc, warm):
+    """Reach-avoid on the periodic double integrator (reach game; an obstacle slab and a box over
+    a corner of the target), upwind + Euler: FP64 takes the oracle's steps to the oracle's values,
+    FP32 + polish lands within its bar; the warm start is the reach solution without the
+    obstacle's corner box."""
+    g, dyn, l, gc = _reach_avoid_periodic_di()
+    opts = dict(spatial=1, temporal=1, cfl=0.8, tol=1e-6, game=1)
+    k = None
+    if warm:
+        k, _ = orc.solve(g, dyn, l, constraint=-W.box_sdf(g, (-0.5, 0.0), (0.1, 0.6)), **opts)
+    print(f"[reach-avoid] warm={warm}", flush=True)
+    Vo, io = orc.solve(g, dyn, l, k, constraint=gc, **opts)
+    assert io["converged"] == 1
+    Vg, rg, st = hjrlib.solve(g, dyn, l, k, constraint=gc, precision=hjrlib.FP64, **opts)
+    assert st == hjrlib.OK and rg["iterations"] == io["steps"]
+    L = np.abs(l).max()
+    assert np.abs(Vg - Vo).max() <= 1e-9 * L
+    assert (Vg >= gc).all() and ((gc > 0) & (l < 0) & (Vg > 0)).any()
+    Vf, rf, st = hjrlib.solve(g, dyn, l, k, constraint=gc, precision=hjrlib.FP32_POLISH64, **opts)
+    band = 1e-4 * L
+    assert st == hjrlib.OK and rf["polish_iterations"] >= 1
+    assert np.abs(Vf - Vo).max() <= band
+    assert _sign_mismatch(Vf, Vo, band) == 0
+
+
+def test_reach_avoid_weno_rk3_fixed_steps_and_device_entry(gpu, hjrlib, orc):
+    """Dubins car, WENO5 + TVD-RK3, reach game with a disk obstacle beside the target disk: 150
+    FP64 steps match the oracle's; the device entry point gives the host entry point's result
+    bitwise."""
+    torch = _torch()
+    p = W.dubins_problem(25, dbar=0.1)
+    gd = -W.disk_sdf(p.grid, (2.5, 0.0), 1.0)
+    opts = dict(spatial=5, temporal=3, cfl=0.5, tol=1e-6, game=1, max_iter=150)
+    Vo, io = orc.solve(p.grid, p.dyn, p.l, constraint=gd, **opts)
+    assert io["steps"] == 150
+    Vg, rg, st = hjrlib.solve(p.grid, p.dyn, p.l, None, constraint=gd, precision=hjrlib.FP64, **opts)
+    assert st == hjrlib.NOT_CONVERGED and rg["iterations"] == 150
+    assert np.abs(Vg - Vo).max() <= 1e-9 * np.abs(p.l).max()
+    lt, gt = torch.tensor(p.l, device="cuda:0"), torch.tensor(gd, device="cuda:0")
+    Vt = torch.empty_like(lt)
+    rd, sd = hjrlib.solve_device(p.grid, p.dyn, lt, None, Vt, constraint=gt, precision=hjrlib.FP64, **opts)
+    torch.cuda.synchronize()
+    assert sd == st and np.array_equal(Vt.cpu().numpy().reshape(p.grid.shape), Vg)
