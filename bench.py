@@ -66,14 +66,17 @@ def parse():
     ap.add_argument("--polish-shift", type=float, default=-1.0, help="FP64 polish start shift (< 0: automatic)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["dubins", "batch", "serve", "control", "quad10", "hbm", "discount"],
+    ap.add_argument("--workload", choices=["dubins", "batch", "serve", "control", "quad10", "hbm", "discount",
+                                           "local"],
                     default="dubins",
                     help="dubins: the headline single-solve benchmark; batch: the 64-instance mixed batch; "
                          "serve: a Poisson request stream through the serving context, warm vs cold; "
                          "control: safe-control queries against the converged 101^3 Dubins value function; "
                          "quad10: the 10-D near-hover quadrotor scenario of Sec. VI by subsystem, warm vs cold; "
                          "hbm: FP32 upwind + Euler steps of the 25^6 quadrotor (the HBM-bound path); "
-                         "discount: standard vs warm-started vs discounted solves (Table 1's comparison)")
+                         "discount: standard vs warm-started vs discounted solves (Table 1's comparison); "
+                         "local: warm-started solves after a local change of the environment, with and "
+                         "without local updates")
     ap.add_argument("--discount", type=float, default=0.999, help="discount: per-step factor (annealed to 1)")
     ap.add_argument("--queries", type=int, default=1 << 20, help="control: query states per batch")
     ap.add_argument("--requests", type=int, default=32, help="serve: number of requests")
@@ -138,6 +141,8 @@ def main():
         return bench_hbm(args)
     if args.workload == "discount":
         return bench_discount(args)
+    if args.workload == "local":
+        return bench_local(args)
     if args.workload == "batch":
         bench_batch(args)
         return
@@ -312,6 +317,81 @@ def bench_discount(args):
         out[name] = res
     print(json.dumps({"workload": "standard-vs-warm-vs-discounted", "discount": args.discount, "problems": out}),
           flush=True)
+
+
+def bench_local(args):
+    """Local updates (Sec. VII): the 101^3 Dubins value function is known; a small obstacle
+    appears (a disk of radius 0.5 at (3, 3)), and the new value function is warm-started from
+    the old one, once updating every node each step and once with local updates (bitwise the
+    same result).  Also the headline warm start (a global change: the disturbance bound) both
+    ways.  Each solve runs once untimed, then `--steps` times timed."""
+    import numpy as np
+    import torch
+
+    from paper_1903_07715_amd import hjr
+    from paper_1903_07715_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    p = W.dubins_problem(n, dbar=0.1)
+    q = W.dubins_problem(n, dbar=0.05)
+    opts = hjr.problem_options(p, precision=hjr.FP32_POLISH64, max_iter=20000)
+    lt = torch.tensor(p.l, device=dev)
+    V0 = torch.empty_like(lt)
+    hjr.solve_device(p.grid, p.dyn, lt, None, V0, **opts)
+    kq = torch.empty_like(lt)
+    hjr.solve_device(q.grid, q.dyn, torch.tensor(q.l, device=dev), None, kq, **dict(opts, precision=hjr.FP64))
+    l2 = torch.tensor(np.minimum(p.l, W.disk_sdf(p.grid, (3.0, 3.0), 0.5)), device=dev)
+    scen = {"new-obstacle": (l2, V0), "disturbance-change": (lt, kq)}
+    out = {}
+    for name, (l, k) in scen.items():
+        res = {}
+        Vs = {}
+        for local in (0, 1):
+            Vt = torch.empty_like(lt)
+            r, st = hjr.solve_device(p.grid, p.dyn, l, k, Vt, local_updates=local, **opts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                r, st = hjr.solve_device(p.grid, p.dyn, l, k, Vt, local_updates=local, **opts)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / args.steps
+            Vs[local] = Vt.cpu().numpy()
+            key = "local" if local else "full"
+            res[key] = {"seconds": el, "steps": [r["iterations"], r["polish_iterations"]],
+                        "node_updates": r["node_updates"], "status": st}
+            log(f"{name} {key}: {res[key]}")
+        res["bitwise_equal"] = bool(np.array_equal(Vs[0], Vs[1]))
+        res["computed_fraction"] = res["local"]["node_updates"] / res["full"]["node_updates"]
+        res["speedup"] = res["full"]["seconds"] / res["local"]["seconds"]
+        out[f"dubins{n}^3-weno5-fp32-polish64 {name}"] = res
+    # the double integrator, upwind + Euler in FP64 (a reach of one node per step), 1001^2
+    d = W.di_box_problem(1001, ubar=1.0, dbar=0.1)
+    dopt = dict(spatial=1, temporal=1, cfl=0.8, tol=1e-6, precision=hjr.FP64, max_iter=100000)
+    dl = torch.tensor(d.l, device=dev)
+    D0 = torch.empty_like(dl)
+    hjr.solve_device(d.grid, d.dyn, dl, None, D0, **dopt)
+    dl2 = torch.tensor(np.minimum(d.l, W.box_sdf(d.grid, (0.6, 0.6), (0.05, 0.05))), device=dev)
+    res = {}
+    Vs = {}
+    for local in (0, 1):
+        Vt = torch.empty_like(dl)
+        r, st = hjr.solve_device(d.grid, d.dyn, dl2, D0, Vt, local_updates=local, **dopt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r, st = hjr.solve_device(d.grid, d.dyn, dl2, D0, Vt, local_updates=local, **dopt)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / args.steps
+        Vs[local] = Vt.cpu().numpy()
+        key = "local" if local else "full"
+        res[key] = {"seconds": el, "steps": r["iterations"], "node_updates": r["node_updates"], "status": st}
+        log(f"di1001 new obstacle {key}: {res[key]}")
+    res["bitwise_equal"] = bool(np.array_equal(Vs[0], Vs[1]))
+    res["computed_fraction"] = res["local"]["node_updates"] / res["full"]["node_updates"]
+    res["speedup"] = res["full"]["seconds"] / res["local"]["seconds"]
+    out["di1001^2-upwind-euler-fp64 new-obstacle"] = res
+    print(json.dumps({"workload": "local-updates", "scenarios": out}), flush=True)
 
 
 def bench_control(args):

@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define HJR_ABI_VERSION 3
+#define HJR_ABI_VERSION 4
 #define HJR_MAX_DIM 6
 #define HJR_MAX_PARAMS 16
 
@@ -153,7 +153,17 @@ typedef struct {
                                ends with V <- min(l, V).  1: the backward reachable set of Sec. II
                                at time t_max: the HJ PDE, eq. (5), with no projection.  Needs
                                t_max > 0, precision HJR_FP64 or HJR_FP32 and no warm start k. */
-    int32_t pad;
+    int32_t local_updates;  /* 0 (default) or 1: update locally (the direction Sec. VII proposes for
+                               local changes of the environment), exactly.  The grid is cut into
+                               blocks of 1024 consecutive nodes; a step recomputes a block only if
+                               a block within its stencils' reach over one step (3 nodes per stage
+                               with WENO5, 1 with upwind, in every dimension) changed in the
+                               previous step, or if the step size, the discount or the phase just
+                               changed.  Otherwise the step would reproduce the block bit for bit,
+                               so results are identical to a full update; only the time differs.
+                               Costs 8 bytes per block and a dependency list per block (built on
+                               the host); where a list would be too long (high dimensions with
+                               WENO5) the solve runs without it. */
     double discount;        /* 0 (default) or 1: none.  In (0, 1): discounted reachability (Sec. II-C):
                                each step ends with V <- min(l, discount * V_step), V_step the
                                result of the time integrator, which makes the step a contraction
@@ -177,6 +187,8 @@ typedef struct {
                                    3 stalled: the change stopped decreasing above tol */
     int32_t pad;
     int64_t discounted_iterations;  /* steps of the first phase taken with a discount < 1 */
+    int64_t node_updates;   /* grid points advanced one step, summed over all steps: steps x nodes,
+                               or fewer with local_updates (the blocks each step computed) */
 } hjr_result;
 
 /* Library information and defaults. */
@@ -213,6 +225,17 @@ hjr_status hjr_solve_reach_avoid_device(const hjr_grid *grid, const hjr_dynamics
                                         const double *l_dev, const double *g_dev,
                                         const double *k_dev, const hjr_options *opts,
                                         double *V_dev, void *stream, hjr_result *result);
+
+/* Local updates (hjr_options.local_updates): the block dependency lists the solver builds for a
+ * grid and a reach (grid steps per dimension: 9 for WENO5 + TVD-RK3, 3 for WENO5 + Euler or
+ * upwind + TVD-RK3, 1 for upwind + Euler).  Blocks are 1024 consecutive nodes of the flattened
+ * grid (last dimension fastest); block b depends on dep[off[b] .. off[b+1]-1], a sorted list that
+ * holds every block with a node within `reach` steps of one of b's nodes (wrapping in periodic
+ * dimensions).  Host arrays: off needs nblocks + 1 entries, dep ndeps; pass NULL for both to
+ * learn the sizes first.  HJR_ERR_UNSUPPORTED when the lists would be too long to be worth it
+ * (a local-updates solve of that grid then updates every block). */
+hjr_status hjr_local_dependencies(const hjr_grid *grid, int32_t reach, int64_t *nblocks, int64_t *ndeps,
+                                  uint32_t *off, uint32_t *dep);
 
 /* Batched solve: `count` independent problems (host arrays) advanced together, every stage of
  * every instance in one launch per stage.  Each problem's status and result are filled in; the

@@ -281,6 +281,7 @@ struct Request {
     const double *k_dev = nullptr;
     const double *g_dev = nullptr;   // reach-avoid constraint function (caller or owned), or null
     double *V_dev = nullptr;         // FP64 output (caller or owned)
+    std::vector<uint32_t> dep_off, dep;  // local updates: block dependency lists (empty: off)
     uint64_t npts = 0;
     size_t bytes = 0;                // working memory
     void *mem = nullptr;             // owned working buffer
@@ -348,7 +349,8 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Working memory of one request, carved from one pool block.
 struct Layout {
-    size_t V32, A32, B32, l32, g32, Vs32, A64, B64, Vs64, V64, l64, k64, g64, tab32, tab64, total;
+    size_t V32, A32, B32, l32, g32, Vs32, A64, B64, Vs64, V64, l64, k64, g64, chg, act, dep_off, dep, tab32, tab64,
+        total;
     int ntab;
 };
 
@@ -375,6 +377,12 @@ static Layout plan_layout(const Request &r, bool own_io, bool has_g)
     L.l64 = own_io ? take(N * 8) : none;
     L.k64 = own_io ? take(N * 8) : none;
     L.g64 = own_io && has_g ? take(N * 8) : none;
+    const bool local = !r.dep_off.empty();
+    const size_t nb = local ? r.dep_off.size() - 1 : 0;
+    L.chg = local ? take(nb * 4) : none;
+    L.act = local ? take(nb * 4) : none;
+    L.dep_off = local ? take(r.dep_off.size() * 4) : none;
+    L.dep = local ? take(r.dep.size() * 4) : none;
     int nt = 0;
     for (int d = 0; d < r.grid.ndim; ++d) nt += r.grid.n[d];
     nt += 2 * r.grid.n[std::min(2, r.grid.ndim - 1)];
@@ -471,6 +479,10 @@ static void build_inst(Request &r, char *base, const Layout &L, std::vector<doub
     I.V64 = r.V_dev;
     I.l64 = r.l_dev;
     I.g64 = r.g_dev;
+    I.chg = (int *)at(L.chg);
+    I.act = (int *)at(L.act);
+    I.dep_off = (const uint32_t *)at(L.dep_off);
+    I.dep = (const uint32_t *)at(L.dep);
     I.state = state_dev;
 }
 
@@ -712,6 +724,12 @@ public:
         std::vector<double> t64;
         std::vector<float> t32;
         build_inst(*r, base, L, t64, t32, d_states_ + slot);
+        if (r->inst.chg) {
+            HJR_HIP(hipMemcpyAsync((void *)r->inst.dep_off, r->dep_off.data(), r->dep_off.size() * 4,
+                                   hipMemcpyHostToDevice, stream_));
+            HJR_HIP(hipMemcpyAsync((void *)r->inst.dep, r->dep.data(), r->dep.size() * 4, hipMemcpyHostToDevice,
+                                   stream_));
+        }
         HJR_HIP(hipMemcpyAsync((void *)r->inst.tab64, t64.data(), t64.size() * 8, hipMemcpyHostToDevice, stream_));
         HJR_HIP(hipMemcpyAsync((void *)r->inst.tab32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice, stream_));
         // the host vectors must outlive the copies
@@ -914,6 +932,7 @@ public:
                 res.polish_iterations = st.n;
             }
             res.discounted_iterations = (r->phase == 0 && st.gamma != 1.0) ? st.n : st.n_disc;
+            res.node_updates = r->inst.chg ? (int64_t)st.node_updates : (int64_t)st.epoch * (int64_t)r->npts;
             res.intervals = st.intervals;
             res.t_final = st.t;
             res.last_delta = st.last_delta;
@@ -1002,7 +1021,7 @@ private:
             if (r->opts.temporal == HJR_TVDRK3) max_stages_ = 3;
             if (r->opts.conv_mode == HJR_CONV_PER_INTERVAL) any_interval_ = true;
             const int fp64 = !(r->phase == 0 && r->fp32_first) ? 1 : 0;
-            G &g = groups[fp64][r->dyn.id * 8 + r->opts.spatial];
+            G &g = groups[fp64][r->dyn.id * 8 + r->opts.spatial + (r->inst.chg ? kLocalKey : 0)];
             g.slots.push_back(i);
             g.nodes += r->npts;
             g.largest = std::max(g.largest, r->npts);
@@ -1012,10 +1031,13 @@ private:
         for (int p = 0; p < 2; ++p) {
             segs_[p].clear();
             for (auto &kv : groups[p]) {
-                const int dyn = kv.first / 8, sp = kv.first % 8;
+                const bool local = kv.first >= kLocalKey;
+                const int dyn = (kv.first % kLocalKey) / 8, sp = kv.first % 8;
                 int npt = kFusedNpt;
                 std::string tkey;
-                if (!fused_) {
+                if (local && !fused_) {
+                    npt = 4;  // the local-update kernels exist for 4 nodes per thread only
+                } else if (!fused_) {
                     npt = npt_override_;
                     if (!npt) {
                         const std::string k = Tuner::key(p, dyn, sp, kv.second.largest);
@@ -1029,7 +1051,8 @@ private:
                 }
                 const int off = (int)t[p].size();
                 append_tiles(kv.second.slots, npt, t[p]);
-                segs_[p].push_back(Seg{dyn, sp, npt, off, (int)t[p].size() - off, (int64_t)kv.second.nodes, tkey});
+                segs_[p].push_back(
+                    Seg{dyn, sp, npt, off, (int)t[p].size() - off, (int64_t)kv.second.nodes, tkey, local});
             }
         }
         n32_ = (int)t[0].size();
@@ -1131,7 +1154,7 @@ private:
                 if (s != HJR_OK) return s;
             }
             HJR_HIP(launch_stage_one(prec != 0, g.dyn, g.spatial, g.npt, d_insts_, tl + g.off, g.count, stage,
-                                     max_blocks_, stream_, ga, gb));
+                                     max_blocks_, stream_, ga, gb, g.local));
             ++launches_;
         }
         return HJR_OK;
@@ -1141,7 +1164,9 @@ private:
         int dyn, spatial, npt, off, count;
         int64_t nodes;         // nodes of the group's instances
         std::string tune_key;  // non-empty: this group is being timed for the autotuner
+        bool local;            // instances with local updates (their own kernel variant)
     };
+    static constexpr int kLocalKey = 1024;  // group key offset of local-update instances
     std::vector<Seg> segs_[2];
     std::map<int, hipGraphExec_t> graphs_by_m_;
     bool graphs_ = false;
@@ -1190,6 +1215,129 @@ struct ChunkPolicy {
     }
 };
 
+// Local updates: for every block of 2^kLocalShift consecutive nodes, the blocks holding a node
+// within `reach` grid steps (per dimension; wrapping in periodic dims) of one of its nodes.  The
+// block's rows (runs along the last dimension) are bounded by a box in the other dimensions,
+// the box is widened by `reach`, and every row in it is taken whole, so the list is a superset
+// of the exact one (which only costs a few extra blocks).  Gives up (lists left empty, local
+// updates off) when a list would be long enough to make the check cost more than it saves.
+static void block_dependencies(const hjr_grid &g, uint64_t N, int reach, std::vector<uint32_t> &off,
+                               std::vector<uint32_t> &dep)
+{
+    const int d = g.ndim, m = d - 1;                // row space: dims 0 .. d-2
+    const uint64_t B = 1ull << kLocalShift, rowlen = (uint64_t)g.n[d - 1];
+    const uint64_t nb = (N + B - 1) / B;
+    const size_t kMaxPerBlock = 256;
+    off.assign(1, 0);
+    dep.clear();
+    std::vector<uint32_t> cur;
+    std::vector<uint32_t> seen(nb, UINT32_MAX);
+    for (uint64_t b = 0; b < nb; ++b) {
+        cur.clear();
+        if (m == 0) {  // 1-D: the block's neighbours along the only dimension
+            const int64_t lo = (int64_t)(b * B) - reach, hi = (int64_t)std::min(N, (b + 1) * B) - 1 + reach;
+            const bool per = g.periodic_mask & 1u;
+            if (per && (lo < 0 || hi >= (int64_t)N)) {
+                for (uint64_t c = 0; c < nb; ++c) cur.push_back((uint32_t)c);
+            } else {
+                for (int64_t c = std::max<int64_t>(lo, 0) / (int64_t)B; c <= std::min<int64_t>(hi, N - 1) / (int64_t)B; ++c)
+                    cur.push_back((uint32_t)c);
+            }
+        } else {
+            // rows of the block and their index box
+            const uint64_t r0 = (b * B) / rowlen, r1 = (std::min(N, (b + 1) * B) - 1) / rowlen;
+            int a0[HJR_MAX_DIM], a1[HJR_MAX_DIM];
+            uint64_t t0 = r0, t1 = r1;
+            for (int j = m - 1; j >= 0; --j) {
+                a0[j] = (int)(t0 % (uint64_t)g.n[j]);
+                a1[j] = (int)(t1 % (uint64_t)g.n[j]);
+                t0 /= (uint64_t)g.n[j];
+                t1 /= (uint64_t)g.n[j];
+            }
+            int lo[HJR_MAX_DIM], hi[HJR_MAX_DIM];
+            bool split = false;
+            for (int j = 0; j < m; ++j) {
+                if (split) {
+                    lo[j] = 0;
+                    hi[j] = g.n[j] - 1;
+                } else {
+                    lo[j] = a0[j];
+                    hi[j] = a1[j];
+                    if (a0[j] != a1[j]) split = true;
+                }
+            }
+            // widen by the reach: per dim a list of index ranges (two when a periodic one wraps)
+            std::vector<std::pair<int, int>> rng[HJR_MAX_DIM];
+            uint64_t combos = 1;
+            for (int j = 0; j < m; ++j) {
+                const int n = g.n[j];
+                const bool per = (g.periodic_mask >> j) & 1u;
+                int l = lo[j] - reach, h = hi[j] + reach;
+                if (per) {
+                    if (h - l + 1 >= n) {
+                        rng[j].push_back({0, n - 1});
+                    } else if (l < 0) {
+                        rng[j].push_back({0, h});
+                        rng[j].push_back({l + n, n - 1});
+                    } else if (h >= n) {
+                        rng[j].push_back({l, n - 1});
+                        rng[j].push_back({0, h - n});
+                    } else {
+                        rng[j].push_back({l, h});
+                    }
+                } else {
+                    rng[j].push_back({std::max(l, 0), std::min(h, n - 1)});
+                }
+                if (j < m - 1) {
+                    uint64_t e = 0;
+                    for (auto &p : rng[j]) e += (uint64_t)(p.second - p.first + 1);
+                    combos *= e;
+                }
+            }
+            if (combos * 2 > kMaxPerBlock * 8) {
+                off.clear();
+                dep.clear();
+                return;
+            }
+            // every combination of the outer dims, then the last row dim's ranges: runs of rows
+            int idx[HJR_MAX_DIM] = {0};
+            std::vector<int> outer_vals[HJR_MAX_DIM];
+            for (int j = 0; j < m - 1; ++j)
+                for (auto &p : rng[j])
+                    for (int v = p.first; v <= p.second; ++v) outer_vals[j].push_back(v);
+            int pos[HJR_MAX_DIM] = {0};
+            for (;;) {
+                uint64_t base = 0;
+                for (int j = 0; j < m - 1; ++j) {
+                    idx[j] = outer_vals[j][pos[j]];
+                    base = base * (uint64_t)g.n[j] + (uint64_t)idx[j];
+                }
+                for (auto &p : rng[m - 1]) {
+                    const uint64_t rs = base * (uint64_t)g.n[m - 1] + (uint64_t)p.first;
+                    const uint64_t re = base * (uint64_t)g.n[m - 1] + (uint64_t)p.second;
+                    const uint64_t f = rs * rowlen / B, l = ((re + 1) * rowlen - 1) / B;
+                    for (uint64_t c = f; c <= l; ++c)
+                        if (seen[c] != (uint32_t)b) {
+                            seen[c] = (uint32_t)b;
+                            cur.push_back((uint32_t)c);
+                        }
+                }
+                int j = m - 2;
+                while (j >= 0 && ++pos[j] == (int)outer_vals[j].size()) pos[j--] = 0;
+                if (j < 0) break;
+            }
+        }
+        if (cur.size() > kMaxPerBlock) {
+            off.clear();
+            dep.clear();
+            return;
+        }
+        std::sort(cur.begin(), cur.end());
+        dep.insert(dep.end(), cur.begin(), cur.end());
+        off.push_back((uint32_t)dep.size());
+    }
+}
+
 static hjr_status prepare(Request &r, const hjr_grid *g, const hjr_dynamics *dy, const hjr_options *o,
                           const void *k)
 {
@@ -1206,6 +1354,7 @@ static hjr_status prepare(Request &r, const hjr_grid *g, const hjr_dynamics *dy,
         return fail(HJR_ERR_INVALID_ARG, "discount must lie in [0, 1]");
     if (o->brs && o->discount > 0.0 && o->discount < 1.0)
         return fail(HJR_ERR_INVALID_ARG, "the reachable-set mode is not discounted");
+    if (o->local_updates != 0 && o->local_updates != 1) return fail(HJR_ERR_INVALID_ARG, "local_updates must be 0 or 1");
     uint64_t N = 0;
     s = validate(g, dy, o->spatial, &N);
     if (s != HJR_OK) return s;
@@ -1213,6 +1362,12 @@ static hjr_status prepare(Request &r, const hjr_grid *g, const hjr_dynamics *dy,
     r.dyn = *dy;
     r.opts = *o;
     r.npts = N;
+    r.dep_off.clear();
+    r.dep.clear();
+    if (o->local_updates) {
+        const int reach = (o->temporal == HJR_TVDRK3 ? 3 : 1) * (o->spatial == HJR_WENO5 ? 3 : 1);
+        block_dependencies(*g, N, reach, r.dep_off, r.dep);
+    }
     return HJR_OK;
 }
 
@@ -1275,7 +1430,7 @@ hjr_status hjr_default_options(hjr_options *o)
     o->max_iter = 100000;
     o->stall_window = 0;
     o->brs = 0;
-    o->pad = 0;
+    o->local_updates = 0;
     o->discount = 0.0;
     return HJR_OK;
 }
@@ -1367,6 +1522,24 @@ hjr_status hjr_solve_device(const hjr_grid *grid, const hjr_dynamics *dyn, const
                             const hjr_options *opts, double *V_dev, void *stream, hjr_result *result)
 {
     return solve_dev(grid, dyn, l_dev, nullptr, k_dev, opts, V_dev, stream, result);
+}
+
+hjr_status hjr_local_dependencies(const hjr_grid *grid, int32_t reach, int64_t *nblocks, int64_t *ndeps,
+                                  uint32_t *off, uint32_t *dep)
+{
+    uint64_t N = 0;
+    hjr_status s = validate_grid(grid, HJR_UPWIND1, &N);
+    if (s != HJR_OK) return s;
+    if (reach < 1 || reach > 64) return fail(HJR_ERR_INVALID_ARG, "reach must lie in 1..64");
+    if (!nblocks || !ndeps) return fail(HJR_ERR_INVALID_ARG, "nblocks and ndeps must not be NULL");
+    std::vector<uint32_t> o, d;
+    block_dependencies(*grid, N, reach, o, d);
+    if (o.empty()) return fail(HJR_ERR_UNSUPPORTED, "the dependency lists would be too long");
+    *nblocks = (int64_t)o.size() - 1;
+    *ndeps = (int64_t)d.size();
+    if (off) std::memcpy(off, o.data(), o.size() * 4);
+    if (dep) std::memcpy(dep, d.data(), d.size() * 4);
+    return HJR_OK;
 }
 
 hjr_status hjr_solve_reach_avoid(const hjr_grid *grid, const hjr_dynamics *dyn, const double *l, const double *g,

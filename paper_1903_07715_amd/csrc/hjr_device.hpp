@@ -18,6 +18,7 @@ namespace hjr {
 
 constexpr int kMaxDim = 6;
 constexpr int kBlock = 256;        // threads per workgroup
+constexpr int kLocalShift = 10;    // local updates: activity is tracked per block of 2^10 nodes
 constexpr int kFusedNpt = 4;       // nodes per thread of the fused (all-model) stage kernel
 
 enum : int { kDynDI = 1, kDynDubins = 2, kDynUnicycle = 3, kDynQuad = 4, kDynQ10XY = 5, kDynQ10Z = 6 };
@@ -59,6 +60,9 @@ struct SolveState {
     int phase;            // 0 first phase, 1 FP64 polish
     double gamma;         // discount factor of the current step (1 = none, always after the anneal)
     long long n_disc;     // steps of the first phase taken with gamma < 1 (set at the anneal)
+    int epoch;            // steps taken in all phases (local updates: the current step's number)
+    int full_epoch;       // local updates: steps up to this epoch compute every block
+    unsigned long long node_updates;  // local updates: grid points of the steps computed so far
 };
 
 // Division by a runtime constant: q = (x * mul) >> (32 + shift), exact for 0 <= x < 2^31.
@@ -111,6 +115,11 @@ struct Inst {
     const double *l64;
     const float *g32;        // reach-avoid constraint function (nullptr: none)
     const double *g64;
+    int *chg;                // local updates (nullptr: off): per node block, the epoch of the
+                             // last step that changed one of its nodes
+    int *act;                // per node block, the epoch of the last step that computed it
+    const uint32_t *dep_off; // per node block, its range in dep: the blocks within the reach of
+    const uint32_t *dep;     // one full step's stencils (itself included)
     float *Vs32;             // interval-mode snapshot (FP32 phase)
     double *Vs64;            // interval-mode snapshot (FP64 phase)
     SolveState *state;

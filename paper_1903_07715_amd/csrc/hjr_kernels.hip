@@ -39,14 +39,15 @@ __device__ __forceinline__ unsigned wave_sum(unsigned v)
 // of workgroups update the same word, so each first reads the word (from L2, relaxed) and
 // issues the atomic only if its value is larger: the word only grows during a launch, so a
 // skipped update was never needed.
-__device__ __forceinline__ void block_max_to(double v, unsigned long long *dst, double *red)
+__device__ __forceinline__ double block_max_to(double v, unsigned long long *dst, double *red)
 {
     v = wave_max(v);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) red[wave] = v;
     __syncthreads();
+    double m = 0.0;
     if (threadIdx.x == 0) {
-        double m = red[0];
+        m = red[0];
 #pragma unroll
         for (int w = 1; w < kBlock / 64; ++w) m = nanmax(m, red[w]);
         const unsigned long long bits = (unsigned long long)__double_as_longlong(m);
@@ -56,6 +57,45 @@ __device__ __forceinline__ void block_max_to(double v, unsigned long long *dst, 
         }
     }
     __syncthreads();
+    return m;  // the workgroup's maximum, in thread 0
+}
+
+// --------------------------------------------------------------------------------------------
+// Local updates (exact): a step's result on a block of nodes depends only on V within the
+// reach of its stencils (nstages x stencil half-width), so when none of those blocks changed
+// in the previous step (and dt, the discount and the phase did not change either), the step
+// would reproduce the block's values bit for bit, and its RK intermediates are the ones still
+// in memory from the last step that computed it.  Such blocks are skipped.
+// --------------------------------------------------------------------------------------------
+
+// Whether the tile [start, start + span) takes part in this stage.  Stage 0 decides for the
+// step and records the decision per block; the later stages read the record, so all stages of
+// a step compute the same tiles.  (Euler: the one stage also marks changes; a flag of the
+// current step seen here only makes the decision more inclusive.)
+__device__ __forceinline__ bool tile_active(const Inst &I, const SolveState *st, uint32_t start, uint32_t span,
+                                            int stage)
+{
+    const int epoch = st->epoch;
+    const uint32_t b0 = start >> kLocalShift;
+    const uint32_t b1 = (min(start + span, I.npts) - 1u) >> kLocalShift;
+    if (stage > 0) {
+        bool a = false;
+        for (uint32_t b = b0; b <= b1; ++b) a |= I.act[b] == epoch;
+        return a;
+    }
+    bool a = epoch <= st->full_epoch;
+    if (!a) {
+        const uint32_t j1 = I.dep_off[b1 + 1];
+        int mine = 0;
+        for (uint32_t j = I.dep_off[b0] + threadIdx.x; j < j1; j += kBlock) mine |= I.chg[I.dep[j]] >= epoch - 1;
+        a = __syncthreads_or(mine) != 0;
+    }
+    if (a && threadIdx.x == 0) {
+        for (uint32_t b = b0; b <= b1; ++b) I.act[b] = epoch;
+        atomicAdd(const_cast<unsigned long long *>(&st->node_updates),
+                  (unsigned long long)(min(start + span, I.npts) - start));
+    }
+    return a;
 }
 
 // --------------------------------------------------------------------------------------------
@@ -99,7 +139,8 @@ __device__ __forceinline__ TileRange xcd_range(int ntiles)
 // Stage kernel
 // --------------------------------------------------------------------------------------------
 
-template <typename T, int DYN, int SPATIAL, int NPT>
+// LOCAL: the instance may use local updates (its changes are then recorded per block).
+template <typename T, int DYN, int SPATIAL, int NPT, bool LOCAL>
 __device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int stage, T dt, double *red)
 {
     using F = Fields<T>;
@@ -160,7 +201,14 @@ __device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int st
             if (node < I.npts) one(node);
         }
     }
-    if (last) block_max_to((double)delta, &st->delta_bits, red);
+    if (last) {
+        const double m = block_max_to((double)delta, &st->delta_bits, red);
+        if (LOCAL && I.chg && threadIdx.x == 0 && (m > 0.0 || m != m)) {
+            const int epoch = st->epoch;
+            const uint32_t b1 = (min(start + (uint32_t)(NPT * kBlock), I.npts) - 1u) >> kLocalShift;
+            for (uint32_t b = start >> kLocalShift; b <= b1; ++b) I.chg[b] = epoch;
+        }
+    }
 }
 
 template <typename T>
@@ -175,29 +223,31 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const Inst *__restrict__ 
         const Inst &I = insts[tl.inst];
         SolveState *st = I.state;
         if (st->done != kRunning || stage >= I.nstages) continue;
+        if (I.chg && !tile_active(I, st, tl.start, (uint32_t)(kFusedNpt * kBlock), stage)) continue;
         const T dt = (T)st->dt_cur;
         const int key = I.dyn * 8 + I.spatial;
         switch (key) {
-        case kDynDI * 8 + kUpwind1: stage_tile<T, kDynDI, kUpwind1, kFusedNpt>(I, tl.start, stage, dt, red); break;
-        case kDynDI * 8 + kWeno5: stage_tile<T, kDynDI, kWeno5, kFusedNpt>(I, tl.start, stage, dt, red); break;
-        case kDynDubins * 8 + kUpwind1: stage_tile<T, kDynDubins, kUpwind1, kFusedNpt>(I, tl.start, stage, dt, red); break;
-        case kDynDubins * 8 + kWeno5: stage_tile<T, kDynDubins, kWeno5, kFusedNpt>(I, tl.start, stage, dt, red); break;
-        case kDynUnicycle * 8 + kUpwind1: stage_tile<T, kDynUnicycle, kUpwind1, kFusedNpt>(I, tl.start, stage, dt, red); break;
-        case kDynUnicycle * 8 + kWeno5: stage_tile<T, kDynUnicycle, kWeno5, kFusedNpt>(I, tl.start, stage, dt, red); break;
-        case kDynQuad * 8 + kUpwind1: stage_tile<T, kDynQuad, kUpwind1, kFusedNpt>(I, tl.start, stage, dt, red); break;
-        case kDynQuad * 8 + kWeno5: stage_tile<T, kDynQuad, kWeno5, kFusedNpt>(I, tl.start, stage, dt, red); break;
-        case kDynQ10XY * 8 + kUpwind1: stage_tile<T, kDynQ10XY, kUpwind1, kFusedNpt>(I, tl.start, stage, dt, red); break;
-        case kDynQ10XY * 8 + kWeno5: stage_tile<T, kDynQ10XY, kWeno5, kFusedNpt>(I, tl.start, stage, dt, red); break;
-        case kDynQ10Z * 8 + kUpwind1: stage_tile<T, kDynQ10Z, kUpwind1, kFusedNpt>(I, tl.start, stage, dt, red); break;
-        case kDynQ10Z * 8 + kWeno5: stage_tile<T, kDynQ10Z, kWeno5, kFusedNpt>(I, tl.start, stage, dt, red); break;
+        case kDynDI * 8 + kUpwind1: stage_tile<T, kDynDI, kUpwind1, kFusedNpt, true>(I, tl.start, stage, dt, red); break;
+        case kDynDI * 8 + kWeno5: stage_tile<T, kDynDI, kWeno5, kFusedNpt, true>(I, tl.start, stage, dt, red); break;
+        case kDynDubins * 8 + kUpwind1: stage_tile<T, kDynDubins, kUpwind1, kFusedNpt, true>(I, tl.start, stage, dt, red); break;
+        case kDynDubins * 8 + kWeno5: stage_tile<T, kDynDubins, kWeno5, kFusedNpt, true>(I, tl.start, stage, dt, red); break;
+        case kDynUnicycle * 8 + kUpwind1: stage_tile<T, kDynUnicycle, kUpwind1, kFusedNpt, true>(I, tl.start, stage, dt, red); break;
+        case kDynUnicycle * 8 + kWeno5: stage_tile<T, kDynUnicycle, kWeno5, kFusedNpt, true>(I, tl.start, stage, dt, red); break;
+        case kDynQuad * 8 + kUpwind1: stage_tile<T, kDynQuad, kUpwind1, kFusedNpt, true>(I, tl.start, stage, dt, red); break;
+        case kDynQuad * 8 + kWeno5: stage_tile<T, kDynQuad, kWeno5, kFusedNpt, true>(I, tl.start, stage, dt, red); break;
+        case kDynQ10XY * 8 + kUpwind1: stage_tile<T, kDynQ10XY, kUpwind1, kFusedNpt, true>(I, tl.start, stage, dt, red); break;
+        case kDynQ10XY * 8 + kWeno5: stage_tile<T, kDynQ10XY, kWeno5, kFusedNpt, true>(I, tl.start, stage, dt, red); break;
+        case kDynQ10Z * 8 + kUpwind1: stage_tile<T, kDynQ10Z, kUpwind1, kFusedNpt, true>(I, tl.start, stage, dt, red); break;
+        case kDynQ10Z * 8 + kWeno5: stage_tile<T, kDynQ10Z, kWeno5, kFusedNpt, true>(I, tl.start, stage, dt, red); break;
         default: break;
         }
     }
 }
 
 // One model and one scheme per kernel: register allocation (and so occupancy) follows that
-// variant alone instead of the largest variant of the fused kernel.
-template <typename T, int DYN, int SPATIAL, int NPT>
+// variant alone instead of the largest variant of the fused kernel.  LOCAL variants serve the
+// instances that use local updates (so the others' kernels carry none of that code).
+template <typename T, int DYN, int SPATIAL, int NPT, bool LOCAL>
 __global__ __launch_bounds__(kBlock) void stage_kernel_one(const Inst *__restrict__ insts,
                                                            const Tile *__restrict__ tiles, int ntiles,
                                                            int stage)
@@ -209,7 +259,8 @@ __global__ __launch_bounds__(kBlock) void stage_kernel_one(const Inst *__restric
         const Inst &I = insts[tl.inst];
         SolveState *st = I.state;
         if (st->done != kRunning || stage >= I.nstages) continue;
-        stage_tile<T, DYN, SPATIAL, NPT>(I, tl.start, stage, (T)st->dt_cur, red);
+        if (LOCAL && !tile_active(I, st, tl.start, (uint32_t)(NPT * kBlock), stage)) continue;
+        stage_tile<T, DYN, SPATIAL, NPT, LOCAL>(I, tl.start, stage, (T)st->dt_cur, red);
     }
 }
 
@@ -235,7 +286,9 @@ __device__ __forceinline__ void apply_limits(SolveState *st)
     } else if (st->t_max > 0.0 && st->t >= st->t_max * (1.0 - 1e-12)) {
         st->done = kHorizon;
     } else {
-        st->dt_cur = next_dt(st);
+        const double dt = next_dt(st);
+        if (dt != st->dt_cur) st->full_epoch = st->epoch;  // another step size: compute in full
+        st->dt_cur = dt;
     }
 }
 
@@ -262,6 +315,7 @@ __device__ __forceinline__ void anneal(SolveState *st, long long count)
     if (st->gamma == 1.0 || (st->done != kConverged && st->done != kStalled)) return;
     st->gamma = 1.0;
     st->n_disc = st->n;
+    st->full_epoch = st->epoch;  // another step function: the next step is computed in full
     st->done = kRunning;
     st->best_delta = INFINITY;
     st->n_best = count;
@@ -276,6 +330,7 @@ __global__ void step_end_kernel(const Inst *__restrict__ insts, int ninst)
     if (st->done != kRunning) return;
     const double dt = st->dt_cur;
     st->n += 1;
+    st->epoch += 1;
     st->t += dt;
     const double delta = __longlong_as_double((long long)st->delta_bits);
     st->delta_bits = 0ull;
@@ -373,6 +428,10 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const Inst *__restrict__ i
             if (fp32) const_cast<float *>(I.g32)[node] = (float)gv;
         }
         lmax = fabs(l);
+        if (I.chg && (node & ((1u << kLocalShift) - 1u)) == 0u) {  // local updates: nothing changed yet
+            I.chg[node >> kLocalShift] = -(1 << 30);
+            I.act[node >> kLocalShift] = -(1 << 30);
+        }
         if (fp32) {
             I.V32[node] = (float)v;
             const_cast<float *>(I.l32)[node] = (float)l;
@@ -449,6 +508,7 @@ __global__ void polish_switch_kernel(const Inst *__restrict__ insts, int inst, d
         st->gamma = 1.0;
     }
     st->phase = 1;
+    st->full_epoch = st->epoch;  // new arrays: the first FP64 step is computed in full
     st->parity = 0;
     st->done = kRunning;
     st->n = 0;
@@ -517,17 +577,17 @@ hipError_t launch_stage(bool fp64, const Inst *insts, const Tile *tiles, int nti
 
 // With ev0/ev1 the launch goes through hipExtLaunchKernel, which stamps the two events with the
 // kernel's own start and end (so their interval is the kernel's duration, without queue gaps).
-template <typename T, int NPT>
+template <typename T, int NPT, bool LOCAL>
 static void launch_one_npt(int dyn, int spatial, dim3 g, hipStream_t s, const Inst *insts, const Tile *tiles,
                            int ntiles, int stage, hipEvent_t ev0, hipEvent_t ev1)
 {
 #define HJR_ONE(D, SP)                                                                                         \
     do {                                                                                                       \
         if (ev0 || ev1)                                                                                        \
-            hipExtLaunchKernelGGL((stage_kernel_one<T, D, SP, NPT>), g, dim3(kBlock), 0, s, ev0, ev1, 0u, insts, \
+            hipExtLaunchKernelGGL((stage_kernel_one<T, D, SP, NPT, LOCAL>), g, dim3(kBlock), 0, s, ev0, ev1, 0u, insts, \
                                   tiles, ntiles, stage);                                                       \
         else                                                                                                   \
-            hipLaunchKernelGGL((stage_kernel_one<T, D, SP, NPT>), g, dim3(kBlock), 0, s, insts, tiles, ntiles,   \
+            hipLaunchKernelGGL((stage_kernel_one<T, D, SP, NPT, LOCAL>), g, dim3(kBlock), 0, s, insts, tiles, ntiles, \
                                stage);                                                                         \
     } while (0)
     const int key = dyn * 8 + spatial;
@@ -550,26 +610,30 @@ static void launch_one_npt(int dyn, int spatial, dim3 g, hipStream_t s, const In
 }
 
 template <typename T>
-static void launch_one(int dyn, int spatial, int npt, dim3 g, hipStream_t s, const Inst *insts, const Tile *tiles,
-                       int ntiles, int stage, hipEvent_t ev0, hipEvent_t ev1)
+static void launch_one(int dyn, int spatial, int npt, bool local, dim3 g, hipStream_t s, const Inst *insts,
+                       const Tile *tiles, int ntiles, int stage, hipEvent_t ev0, hipEvent_t ev1)
 {
+    if (local) {  // local-update groups always use 4 nodes per thread
+        launch_one_npt<T, 4, true>(dyn, spatial, g, s, insts, tiles, ntiles, stage, ev0, ev1);
+        return;
+    }
     switch (npt) {
-    case 1: launch_one_npt<T, 1>(dyn, spatial, g, s, insts, tiles, ntiles, stage, ev0, ev1); break;
-    case 2: launch_one_npt<T, 2>(dyn, spatial, g, s, insts, tiles, ntiles, stage, ev0, ev1); break;
-    case 8: launch_one_npt<T, 8>(dyn, spatial, g, s, insts, tiles, ntiles, stage, ev0, ev1); break;
-    default: launch_one_npt<T, 4>(dyn, spatial, g, s, insts, tiles, ntiles, stage, ev0, ev1); break;
+    case 1: launch_one_npt<T, 1, false>(dyn, spatial, g, s, insts, tiles, ntiles, stage, ev0, ev1); break;
+    case 2: launch_one_npt<T, 2, false>(dyn, spatial, g, s, insts, tiles, ntiles, stage, ev0, ev1); break;
+    case 8: launch_one_npt<T, 8, false>(dyn, spatial, g, s, insts, tiles, ntiles, stage, ev0, ev1); break;
+    default: launch_one_npt<T, 4, false>(dyn, spatial, g, s, insts, tiles, ntiles, stage, ev0, ev1); break;
     }
 }
 
 hipError_t launch_stage_one(bool fp64, int dyn, int spatial, int npt, const Inst *insts, const Tile *tiles, int ntiles,
-                            int stage, int max_blocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+                            int stage, int max_blocks, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, bool local)
 {
     if (ntiles <= 0) return hipSuccess;
     const dim3 g(grid_for(ntiles, max_blocks));
     if (fp64)
-        launch_one<double>(dyn, spatial, npt, g, s, insts, tiles, ntiles, stage, ev0, ev1);
+        launch_one<double>(dyn, spatial, npt, local, g, s, insts, tiles, ntiles, stage, ev0, ev1);
     else
-        launch_one<float>(dyn, spatial, npt, g, s, insts, tiles, ntiles, stage, ev0, ev1);
+        launch_one<float>(dyn, spatial, npt, local, g, s, insts, tiles, ntiles, stage, ev0, ev1);
     return hipGetLastError();
 }
 

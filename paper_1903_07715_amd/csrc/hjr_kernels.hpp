@@ -10,7 +10,7 @@ hipError_t launch_stage(bool fp64, const Inst *insts, const Tile *tiles, int nti
 // ev0/ev1 (optional): events stamped with the kernel's own start and end
 hipError_t launch_stage_one(bool fp64, int dyn, int spatial, int npt, const Inst *insts, const Tile *tiles, int ntiles,
                             int stage, int max_blocks, hipStream_t s, hipEvent_t ev0 = nullptr,
-                            hipEvent_t ev1 = nullptr);
+                            hipEvent_t ev1 = nullptr, bool local = false);
 hipError_t launch_step_end(const Inst *insts, int ninst, hipStream_t s);
 hipError_t launch_interval(bool fp64, const Inst *insts, const Tile *tiles, int ntiles, int max_blocks,
                            hipStream_t s);

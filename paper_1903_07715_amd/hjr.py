@@ -31,7 +31,7 @@ EXPORTED = ["hjr_abi_version", "hjr_default_options", "hjr_status_string", "hjr_
             "hjr_stage_device", "hjr_ctx_create", "hjr_submit", "hjr_poll", "hjr_ctx_drain",
             "hjr_ctx_get_stats", "hjr_ctx_destroy", "hjr_profile_enable", "hjr_profile_read",
             "hjr_num_controls", "hjr_gradient_device", "hjr_safe_control_device", "hjr_solve_reach_avoid",
-            "hjr_solve_reach_avoid_device"]
+            "hjr_solve_reach_avoid_device", "hjr_local_dependencies"]
 
 
 class Grid_(C.Structure):
@@ -49,14 +49,14 @@ class Options_(C.Structure):
                 ("cfl", C.c_double), ("tol", C.c_double), ("tol_fp32", C.c_double),
                 ("polish_shift", C.c_double), ("dt_report", C.c_double), ("t_max", C.c_double),
                 ("dt_max", C.c_double), ("max_iter", C.c_int64), ("stall_window", C.c_int64),
-                ("brs", C.c_int32), ("pad", C.c_int32), ("discount", C.c_double)]
+                ("brs", C.c_int32), ("local_updates", C.c_int32), ("discount", C.c_double)]
 
 
 class Result_(C.Structure):
     _fields_ = [("iterations", C.c_int64), ("polish_iterations", C.c_int64), ("intervals", C.c_int64),
                 ("t_final", C.c_double), ("last_delta", C.c_double), ("dt", C.c_double),
                 ("max_abs_l", C.c_double), ("seconds", C.c_double), ("converged", C.c_int32),
-                ("pad", C.c_int32), ("discounted_iterations", C.c_int64)]
+                ("pad", C.c_int32), ("discounted_iterations", C.c_int64), ("node_updates", C.c_int64)]
 
 
 class Problem_(C.Structure):
@@ -118,6 +118,7 @@ def load():
         lib.hjr_solve_reach_avoid_device.argtypes = [P(Grid_), P(Dynamics_), vp, vp, vp, P(Options_), vp, vp,
                                                      P(Result_)]
         lib.hjr_batch_solve.argtypes = [C.c_int32, P(Problem_)]
+        lib.hjr_local_dependencies.argtypes = [P(Grid_), C.c_int32, P(C.c_int64), P(C.c_int64), vp, vp]
         lib.hjr_cfl_dt.argtypes = [P(Grid_), P(Dynamics_), C.c_double, C.c_double, dp]
         lib.hjr_stage_device.argtypes = [P(Grid_), P(Dynamics_), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                          C.c_int32, C.c_double, vp, vp, vp, vp, dp, vp]
@@ -285,6 +286,17 @@ def batch_solve(problems: Sequence, ls: Sequence[np.ndarray], ks: Sequence[Optio
     if st < 0:
         raise HJRError(st, last_error())
     return outs, [result_dict(arr[i].result) for i in range(n)], [int(arr[i].status) for i in range(n)]
+
+
+def local_dependencies(grid, reach: int):
+    """hjr_local_dependencies: (off, dep) uint32 arrays of the block dependency lists."""
+    nb, nd = C.c_int64(), C.c_int64()
+    gs = grid_struct(grid)
+    _check(load().hjr_local_dependencies(C.byref(gs), reach, C.byref(nb), C.byref(nd), None, None))
+    off = np.empty(nb.value + 1, dtype=np.uint32)
+    dep = np.empty(max(nd.value, 1), dtype=np.uint32)
+    _check(load().hjr_local_dependencies(C.byref(gs), reach, C.byref(nb), C.byref(nd), off.ctypes.data, dep.ctypes.data))
+    return off, dep[:nd.value]
 
 
 def cfl_dt(grid, dyn, cfl=0.5, dt_max=0.0) -> float:

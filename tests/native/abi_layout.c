@@ -11,8 +11,8 @@ int main(void)
            sizeof(hjr_grid), sizeof(hjr_dynamics), sizeof(hjr_options), sizeof(hjr_result), sizeof(hjr_problem),
            sizeof(hjr_ctx_stats));
     F(hjr_grid, lo); F(hjr_grid, periodic_mask);
-    F(hjr_options, cfl); F(hjr_options, max_iter); F(hjr_options, stall_window); F(hjr_options, brs); F(hjr_options, discount);
-    F(hjr_result, seconds); F(hjr_result, converged); F(hjr_result, discounted_iterations);
+    F(hjr_options, cfl); F(hjr_options, max_iter); F(hjr_options, stall_window); F(hjr_options, brs); F(hjr_options, discount); F(hjr_options, local_updates);
+    F(hjr_result, seconds); F(hjr_result, converged); F(hjr_result, discounted_iterations); F(hjr_result, node_updates);
     F(hjr_problem, opts); F(hjr_problem, l); F(hjr_problem, result); F(hjr_problem, status);
     return 0;
 }

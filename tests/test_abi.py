@@ -1,6 +1,7 @@
 """CPU checks of the C ABI: the library loads, exports every symbol include/hjr.h declares, and
 rejects bad arguments before touching a device.  No compute call runs here."""
 import ctypes as C
+import itertools
 import os
 import re
 import subprocess
@@ -55,7 +56,7 @@ def test_struct_layouts_match_header():
 
 
 def test_defaults_and_strings():
-    assert hjr.abi_version() == 3
+    assert hjr.abi_version() == 4
     o = hjr.options()
     assert (o.spatial, o.temporal, o.precision, o.cfl, o.tol) == (hjr.WENO5, hjr.TVDRK3, hjr.FP32_POLISH64, 0.5, 1e-6)
     lib = hjr.load()
@@ -228,3 +229,50 @@ def test_reach_avoid_arguments():
     st = lib.hjr_solve_reach_avoid_device(C.byref(hjr.grid_struct(g)), C.byref(hjr.dyn_struct(d)), None, None, None,
                                           C.byref(hjr.options()), None, None, C.byref(res))
     assert st == hjr.ERR_INVALID_ARG
+
+
+def _dependency_pairs_ok(grid, reach):
+    """Every node within `reach` steps (per dimension; wrapping where periodic) of a node of
+    block b must lie in a block of b's list (brute force over all offsets)."""
+    off, dep = hjr.local_dependencies(grid, reach)
+    B = 1024
+    n = np.array(grid.n)
+    N = int(np.prod(n))
+    nb = (N + B - 1) // B
+    assert off.shape[0] == nb + 1 and off[0] == 0 and off[-1] == dep.shape[0]
+    allowed = np.zeros((nb, nb), dtype=bool)
+    for b in range(nb):
+        lst = dep[off[b]:off[b + 1]]
+        assert np.all(np.diff(lst.astype(np.int64)) > 0) and b in lst
+        allowed[b, lst] = True
+    idx = np.stack(np.unravel_index(np.arange(N), grid.shape), 1)
+    src = np.arange(N) // B
+    for o in itertools.product(range(-reach, reach + 1), repeat=grid.ndim):
+        j = idx + np.array(o)
+        ok = np.ones(N, dtype=bool)
+        for d in range(grid.ndim):
+            if grid.periodic[d]:
+                j[:, d] %= n[d]
+            else:
+                ok &= (j[:, d] >= 0) & (j[:, d] < n[d])
+        flat = np.ravel_multi_index(tuple(j[ok].T), grid.shape)
+        assert allowed[src[ok], flat // B].all(), o
+    return dep.shape[0] / nb
+
+
+@pytest.mark.parametrize("case", [
+    ("2-D WENO5+RK3", W.Grid((301, 257), (-1, -1), (1, 1), (False, True)), 9),
+    ("3-D reach 3", W.Grid((40, 37, 45), (-1, -1, -1), (1, 1, 1), (True, False, True)), 3),
+    ("4-D reach 3", W.Grid((13, 12, 15, 11), (-1,) * 4, (1,) * 4, (False, True, False, False)), 3),
+    ("6-D upwind+Euler", W.Grid((6, 7, 5, 6, 7, 5), (-1,) * 6, (1,) * 6), 1),
+], ids=lambda c: c[0])
+def test_local_update_dependency_lists_cover_the_stencil_reach(case):
+    _, grid, reach = case
+    per_block = _dependency_pairs_ok(grid, reach)
+    assert per_block < 256
+
+
+def test_local_dependencies_refused_when_too_long():
+    g = W.Grid((25,) * 6, (-1,) * 6, (1,) * 6)
+    with pytest.raises(hjr.HJRError):
+        hjr.local_dependencies(g, 9)
