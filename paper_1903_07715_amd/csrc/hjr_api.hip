@@ -349,8 +349,7 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Working memory of one request, carved from one pool block.
 struct Layout {
-    size_t V32, A32, B32, l32, g32, Vs32, A64, B64, Vs64, V64, l64, k64, g64, chg, act, dep_off, dep, tab32, tab64,
-        total;
+    size_t V32, A32, B32, l32, g32, Vs32, A64, B64, Vs64, V64, l64, k64, g64, act, dep_off, dep, tab32, tab64, total;
     int ntab;
 };
 
@@ -379,8 +378,7 @@ static Layout plan_layout(const Request &r, bool own_io, bool has_g)
     L.g64 = own_io && has_g ? take(N * 8) : none;
     const bool local = !r.dep_off.empty();
     const size_t nb = local ? r.dep_off.size() - 1 : 0;
-    L.chg = local ? take(nb * 4) : none;
-    L.act = local ? take(nb * 4) : none;
+    L.act = local ? take(2 * nb * 4) : none;
     L.dep_off = local ? take(r.dep_off.size() * 4) : none;
     L.dep = local ? take(r.dep.size() * 4) : none;
     int nt = 0;
@@ -479,8 +477,8 @@ static void build_inst(Request &r, char *base, const Layout &L, std::vector<doub
     I.V64 = r.V_dev;
     I.l64 = r.l_dev;
     I.g64 = r.g_dev;
-    I.chg = (int *)at(L.chg);
     I.act = (int *)at(L.act);
+    I.nblocks = r.dep_off.empty() ? 0u : (uint32_t)(r.dep_off.size() - 1);
     I.dep_off = (const uint32_t *)at(L.dep_off);
     I.dep = (const uint32_t *)at(L.dep);
     I.state = state_dev;
@@ -724,7 +722,7 @@ public:
         std::vector<double> t64;
         std::vector<float> t32;
         build_inst(*r, base, L, t64, t32, d_states_ + slot);
-        if (r->inst.chg) {
+        if (r->inst.act) {
             HJR_HIP(hipMemcpyAsync((void *)r->inst.dep_off, r->dep_off.data(), r->dep_off.size() * 4,
                                    hipMemcpyHostToDevice, stream_));
             HJR_HIP(hipMemcpyAsync((void *)r->inst.dep, r->dep.data(), r->dep.size() * 4, hipMemcpyHostToDevice,
@@ -932,7 +930,7 @@ public:
                 res.polish_iterations = st.n;
             }
             res.discounted_iterations = (r->phase == 0 && st.gamma != 1.0) ? st.n : st.n_disc;
-            res.node_updates = r->inst.chg ? (int64_t)st.node_updates : (int64_t)st.epoch * (int64_t)r->npts;
+            res.node_updates = r->inst.act ? (int64_t)st.node_updates : (int64_t)st.epoch * (int64_t)r->npts;
             res.intervals = st.intervals;
             res.t_final = st.t;
             res.last_delta = st.last_delta;
@@ -1021,7 +1019,7 @@ private:
             if (r->opts.temporal == HJR_TVDRK3) max_stages_ = 3;
             if (r->opts.conv_mode == HJR_CONV_PER_INTERVAL) any_interval_ = true;
             const int fp64 = !(r->phase == 0 && r->fp32_first) ? 1 : 0;
-            G &g = groups[fp64][r->dyn.id * 8 + r->opts.spatial + (r->inst.chg ? kLocalKey : 0)];
+            G &g = groups[fp64][r->dyn.id * 8 + r->opts.spatial + (r->inst.act ? kLocalKey : 0)];
             g.slots.push_back(i);
             g.nodes += r->npts;
             g.largest = std::max(g.largest, r->npts);

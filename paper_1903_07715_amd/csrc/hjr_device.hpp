@@ -115,9 +115,9 @@ struct Inst {
     const double *l64;
     const float *g32;        // reach-avoid constraint function (nullptr: none)
     const double *g64;
-    int *chg;                // local updates (nullptr: off): per node block, the epoch of the
-                             // last step that changed one of its nodes
-    int *act;                // per node block, the epoch of the last step that computed it
+    int *act;                // local updates (nullptr: off): two arrays of nblocks; act[e & 1][b]
+                             // == e marks block b for step e
+    uint32_t nblocks;        // node blocks of 2^kLocalShift nodes
     const uint32_t *dep_off; // per node block, its range in dep: the blocks within the reach of
     const uint32_t *dep;     // one full step's stencils (itself included)
     float *Vs32;             // interval-mode snapshot (FP32 phase)

@@ -68,34 +68,32 @@ __device__ __forceinline__ double block_max_to(double v, unsigned long long *dst
 // in memory from the last step that computed it.  Such blocks are skipped.
 // --------------------------------------------------------------------------------------------
 
-// Whether the tile [start, start + span) takes part in this stage.  Stage 0 decides for the
-// step and records the decision per block; the later stages read the record, so all stages of
-// a step compute the same tiles.  (Euler: the one stage also marks changes; a flag of the
-// current step seen here only makes the decision more inclusive.)
-__device__ __forceinline__ bool tile_active(const Inst &I, const SolveState *st, uint32_t start, uint32_t span,
-                                            int stage)
+// Whether the tile [start, start + span) takes part in this step: a full step, or one of its
+// blocks was marked for this step by a block that changed in the previous one.  The marks of
+// step e live in act[e & 1] (act holds two arrays of nblocks), which no stage of step e
+// writes, so every stage of the step takes the same decision.
+__device__ __forceinline__ bool tile_active(const Inst &I, const SolveState *st, uint32_t start, uint32_t span)
 {
     const int epoch = st->epoch;
+    if (epoch <= st->full_epoch) return true;
+    const int *act = I.act + ((epoch & 1) ? I.nblocks : 0u);
+    const uint32_t b1 = (min(start + span, I.npts) - 1u) >> kLocalShift;
+    bool a = false;
+    for (uint32_t b = start >> kLocalShift; b <= b1; ++b) a |= act[b] == epoch;
+    return a;
+}
+
+// After the last stage of a tile whose values changed: mark every block whose next step
+// depends on the tile's blocks (the dependency relation is symmetric; the lists are supersets
+// of it) for the next step.  All threads of the workgroup share the stores.
+__device__ __forceinline__ void mark_dependents(const Inst &I, const SolveState *st, uint32_t start, uint32_t span)
+{
+    const int next = st->epoch + 1;
+    int *act = I.act + ((next & 1) ? I.nblocks : 0u);
     const uint32_t b0 = start >> kLocalShift;
     const uint32_t b1 = (min(start + span, I.npts) - 1u) >> kLocalShift;
-    if (stage > 0) {
-        bool a = false;
-        for (uint32_t b = b0; b <= b1; ++b) a |= I.act[b] == epoch;
-        return a;
-    }
-    bool a = epoch <= st->full_epoch;
-    if (!a) {
-        const uint32_t j1 = I.dep_off[b1 + 1];
-        int mine = 0;
-        for (uint32_t j = I.dep_off[b0] + threadIdx.x; j < j1; j += kBlock) mine |= I.chg[I.dep[j]] >= epoch - 1;
-        a = __syncthreads_or(mine) != 0;
-    }
-    if (a && threadIdx.x == 0) {
-        for (uint32_t b = b0; b <= b1; ++b) I.act[b] = epoch;
-        atomicAdd(const_cast<unsigned long long *>(&st->node_updates),
-                  (unsigned long long)(min(start + span, I.npts) - start));
-    }
-    return a;
+    const uint32_t j1 = I.dep_off[b1 + 1];
+    for (uint32_t j = I.dep_off[b0] + threadIdx.x; j < j1; j += kBlock) act[I.dep[j]] = next;
 }
 
 // --------------------------------------------------------------------------------------------
@@ -202,11 +200,17 @@ __device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int st
         }
     }
     if (last) {
-        const double m = block_max_to((double)delta, &st->delta_bits, red);
-        if (LOCAL && I.chg && threadIdx.x == 0 && (m > 0.0 || m != m)) {
-            const int epoch = st->epoch;
-            const uint32_t b1 = (min(start + (uint32_t)(NPT * kBlock), I.npts) - 1u) >> kLocalShift;
-            for (uint32_t b = start >> kLocalShift; b <= b1; ++b) I.chg[b] = epoch;
+        block_max_to((double)delta, &st->delta_bits, red);
+        if (LOCAL && I.act) {
+            // every thread reads the per-wave maxima block_max_to left in red
+            double m = red[0];
+#pragma unroll
+            for (int w = 1; w < kBlock / 64; ++w) m = nanmax(m, red[w]);
+            __syncthreads();  // red is rewritten by the next tile of a persistent grid
+            const uint32_t span = (uint32_t)(NPT * kBlock);
+            if (m > 0.0 || m != m) mark_dependents(I, st, start, span);
+            if (threadIdx.x == 0)
+                atomicAdd(&st->node_updates, (unsigned long long)(min(start + span, I.npts) - start));
         }
     }
 }
@@ -223,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const Inst *__restrict__ 
         const Inst &I = insts[tl.inst];
         SolveState *st = I.state;
         if (st->done != kRunning || stage >= I.nstages) continue;
-        if (I.chg && !tile_active(I, st, tl.start, (uint32_t)(kFusedNpt * kBlock), stage)) continue;
+        if (I.act && !tile_active(I, st, tl.start, (uint32_t)(kFusedNpt * kBlock))) continue;
         const T dt = (T)st->dt_cur;
         const int key = I.dyn * 8 + I.spatial;
         switch (key) {
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel_one(const Inst *__restric
         const Inst &I = insts[tl.inst];
         SolveState *st = I.state;
         if (st->done != kRunning || stage >= I.nstages) continue;
-        if (LOCAL && !tile_active(I, st, tl.start, (uint32_t)(NPT * kBlock), stage)) continue;
+        if (LOCAL && !tile_active(I, st, tl.start, (uint32_t)(NPT * kBlock))) continue;
         stage_tile<T, DYN, SPATIAL, NPT, LOCAL>(I, tl.start, stage, (T)st->dt_cur, red);
     }
 }
@@ -428,9 +432,9 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const Inst *__restrict__ i
             if (fp32) const_cast<float *>(I.g32)[node] = (float)gv;
         }
         lmax = fabs(l);
-        if (I.chg && (node & ((1u << kLocalShift) - 1u)) == 0u) {  // local updates: nothing changed yet
-            I.chg[node >> kLocalShift] = -(1 << 30);
+        if (I.act && (node & ((1u << kLocalShift) - 1u)) == 0u) {  // local updates: no marks yet
             I.act[node >> kLocalShift] = -(1 << 30);
+            I.act[I.nblocks + (node >> kLocalShift)] = -(1 << 30);
         }
         if (fp32) {
             I.V32[node] = (float)v;
