@@ -77,7 +77,8 @@ def parse():
                          "discount: standard vs warm-started vs discounted solves (Table 1's comparison); "
                          "local: warm-started solves after a local change of the environment, with and "
                          "without local updates")
-    ap.add_argument("--discount", type=float, default=0.999, help="discount: per-step factor (annealed to 1)")
+    ap.add_argument("--discount", type=float, default=None,
+                    help="discount: per-step factor, annealed to 1 (default: Table 1's 0.999)")
     ap.add_argument("--queries", type=int, default=1 << 20, help="control: query states per batch")
     ap.add_argument("--requests", type=int, default=32, help="serve: number of requests")
     ap.add_argument("--quad-n", type=int, default=25, help="serve: grid side of the 6-D quadrotor requests")
@@ -283,6 +284,8 @@ def bench_discount(args):
     from paper_1903_07715_amd import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.discount is None:
+        args.discount = W.TABLE1_DISCOUNT
     out = {}
     probs = [("dubins3d-%d^3-weno5-tvdrk3-fp32-polish64" % args.n, W.dubins_problem(args.n, dbar=0.1),
               W.dubins_problem(args.n, dbar=0.05), dict(precision=hjr.FP32_POLISH64)),
@@ -473,13 +476,15 @@ def bench_quad10(args):
             res = [ctx.poll(t) for t in ts]
         return outs, res, time.perf_counter() - t0
 
-    base = W.quad10_problems(m=5.0, dbar_xy=1.0, n_xy=nxy, n_z=nz)
+    m0, d0 = W.QUAD10_SCENARIOS["base"]
+    base = W.quad10_problems(m=m0, dbar_xy=d0, n_xy=nxy, n_z=nz)
     run(base, [None] * 3)  # warm-up (tuning, first-touch allocation)
     Vb, rb, tb = run(base, [None] * 3)
     log(f"quad10 base: {[r['iterations'] + r['polish_iterations'] for _, r in rb]} steps, {tb:.3f} s")
     out = {"workload": f"quad10-subsystems-xy{nxy}^4-z{nz}^2-upwind-euler-fp32-polish64",
            "base_steps": [r["iterations"] + r["polish_iterations"] for _, r in rb], "base_seconds": tb}
-    for tag, m, dxy in (("heavier", 5.25, 1.5), ("lighter", 4.8, 0.95)):
+    for tag in ("heavier", "lighter"):
+        m, dxy = W.QUAD10_SCENARIOS[tag]
         new = W.quad10_problems(m=m, dbar_xy=dxy, n_xy=nxy, n_z=nz)
         Vc, rc, tc = run(new, [None] * 3)
         Vw, rw, tw = run(new, Vb)

@@ -135,6 +135,13 @@ def quad6(m=1.2, dbar=(0.5, 0.5, 0.5), g=9.81, phi_max=0.3, theta_max=0.3, tmin=
 G = 9.81
 
 
+# The scenario of Sec. VI: (mass, horizontal disturbance bound) before and after the change.
+QUAD10_SCENARIOS = {"base": (5.0, 1.0), "heavier": (5.25, 1.5), "lighter": (4.8, 0.95)}
+
+# The per-step discount factor of the discounted-reachability comparison (Sec. V, Table 1).
+TABLE1_DISCOUNT = 0.999
+
+
 def quad10_xy(dbar=1.0, g=G, d0=10.0, d1=8.0, n0=10.0, smax=math.radians(10.0)) -> Dynamics:
     """Horizontal subsystem (p, v, theta, omega): p' = v + d, v' = g tan(theta),
     theta' = -d1 theta + omega, omega' = -d0 theta + n0 S, |S| <= smax, |d| <= dbar."""

@@ -7,7 +7,9 @@ explicit lattice searches for the Hamiltonian's max-min (eq. (6)).  A plausible 
 in the oracle -- a dropped WENO term, a wrong dissipation sign, a swapped max/min, a wrong RK3
 coefficient, a transposed stencil -- fails at least one of these.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -364,7 +366,9 @@ def test_theorem2_and_propositions_exact(orc):
     Vw, iw = orc.solve(q1.grid, q1.dyn, q1.l, V0, **orc.problem_opts(q1))
     assert np.abs(V0 - V1).max() > 0.05 and np.abs(Vw - V1).max() < 1e-6
 
-    s0, s1 = W.di_strip_problem(41, b=1.0), W.di_strip_problem(41, b=0.8)
+    cac = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_parameters.json")))
+    cac = cac["control_authority_change"]  # the paper's b values
+    s0, s1 = W.di_strip_problem(41, b=cac["b_before"]), W.di_strip_problem(41, b=cac["b_after"])
     S0, _ = orc.solve(s0.grid, s0.dyn, s0.l, **orc.problem_opts(s0))
     S1, j1 = orc.solve(s1.grid, s1.dyn, s1.l, **orc.problem_opts(s1))
     Sw, jw = orc.solve(s1.grid, s1.dyn, s1.l, S0, **orc.problem_opts(s1))
