@@ -21,7 +21,12 @@
  *                 with alpha_i(x) = max over (u, d) of |f_i(x, u, d)|.
  *   time          backward time s = -t; HJR_EULER: V + dt L(V); HJR_TVDRK3: the three-stage
  *                 Shu-Osher scheme.  dt = cfl / max_x sum_i alpha_i(x)/dx_i (fixed per solve).
- *   projection    V <- min(l, V) after every full step (eq. (7)).
+ *   projection    V <- min(l, V) after every full step (eq. (7)).  Variants, all options of the
+ *                 same solver: none at all (brs: the backward reachable set, Sec. II); the step's
+ *                 result times a discount factor before it (discounted reachability, Sec. II-C);
+ *                 max(g, .) after it (reach-avoid with a constraint function g).
+ *   local updates optional exact skipping of node blocks whose neighbourhood did not change
+ *                 (the local updating of Sec. VII); results are bitwise those of full updates.
  *   stopping      HJR_CONV_PER_STEP: stop when max_x |V^{n+1} - V^n| < tol.
  *                 HJR_CONV_PER_INTERVAL: steps are cut to end on multiples of dt_report and the
  *                 change across a whole interval is tested (the rule of Sec. IV: interval 0.01,
