@@ -125,3 +125,30 @@ def test_batch_mixes_local_and_full_instances(gpu, hjrlib):
         Va, ra, sa = hjrlib.solve(pp.grid, pp.dyn, ll, kk, **dict(o, local_updates=0))
         assert st == sa and np.array_equal(V, Va)
         assert (r["iterations"], r["polish_iterations"]) == (ra["iterations"], ra["polish_iterations"])
+
+
+def test_serving_context_local_updates_bitwise(gpu, hjrlib):
+    """Requests with local updates through the serving context, beside one without: each result
+    is bitwise the full-update solve's."""
+    torch = __import__("torch")
+    d = W.di_box_problem(301, ubar=1.0, dbar=0.1)
+    opts = dict(spatial=1, temporal=1, cfl=0.8, tol=1e-6, precision=0)
+    V0, _, _ = hjrlib.solve(d.grid, d.dyn, d.l, None, **opts)
+    l2 = np.minimum(d.l, W.box_sdf(d.grid, (0.6, 0.6), (0.05, 0.05)))
+    p = W.dubins_problem(31)
+    cases = [(d, l2, V0, dict(opts, local_updates=1)), (d, l2, V0, opts),
+             (p, p.l, None, dict(hjrlib.problem_options(p), local_updates=1))]
+    dev = "cuda:0"
+    ls = [torch.tensor(c[1], device=dev) for c in cases]
+    ks = [None if c[2] is None else torch.tensor(c[2], device=dev) for c in cases]
+    outs = [torch.empty_like(l) for l in ls]
+    with hjrlib.Context(0) as ctx:
+        ts = [ctx.submit(c[0].grid, c[0].dyn, l, k, V, **c[3]) for c, l, k, V in zip(cases, ls, ks, outs)]
+        ctx.drain()
+        res = [ctx.poll(t) for t in ts]
+    torch.cuda.synchronize()
+    for c, V, (st, r) in zip(cases, outs, res):
+        Va, ra, sa = hjrlib.solve(c[0].grid, c[0].dyn, c[1], c[2], **dict(c[3], local_updates=0))
+        assert st == sa and r["iterations"] == ra["iterations"]
+        assert np.array_equal(V.cpu().numpy().reshape(c[0].grid.shape), Va)
+    assert res[0][1]["node_updates"] < res[1][1]["node_updates"]
