@@ -166,8 +166,8 @@ typedef struct {
                                previous step, or if the step size, the discount or the phase just
                                changed.  Otherwise the step would reproduce the block bit for bit,
                                so results are identical to a full update; only the time differs.
-                               Costs 8 bytes per block and a dependency list per block (built on
-                               the host); where a list would be too long (high dimensions with
+                               Costs 16 bytes per block and a dependency list per block (built
+                               on the host); where a list would be too long (high dimensions with
                                WENO5) the solve runs without it. */
     double discount;        /* 0 (default) or 1: none.  In (0, 1): discounted reachability (Sec. II-C):
                                each step ends with V <- min(l, discount * V_step), V_step the

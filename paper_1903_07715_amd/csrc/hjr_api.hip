@@ -349,7 +349,8 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Working memory of one request, carved from one pool block.
 struct Layout {
-    size_t V32, A32, B32, l32, g32, Vs32, A64, B64, Vs64, V64, l64, k64, g64, act, dep_off, dep, tab32, tab64, total;
+    size_t V32, A32, B32, l32, g32, Vs32, A64, B64, Vs64, V64, l64, k64, g64, act, cnt, dep_off, dep, tab32, tab64,
+        total;
     int ntab;
 };
 
@@ -379,6 +380,7 @@ static Layout plan_layout(const Request &r, bool own_io, bool has_g)
     const bool local = !r.dep_off.empty();
     const size_t nb = local ? r.dep_off.size() - 1 : 0;
     L.act = local ? take(2 * nb * 4) : none;
+    L.cnt = local ? take(nb * 8) : none;
     L.dep_off = local ? take(r.dep_off.size() * 4) : none;
     L.dep = local ? take(r.dep.size() * 4) : none;
     int nt = 0;
@@ -478,6 +480,7 @@ static void build_inst(Request &r, char *base, const Layout &L, std::vector<doub
     I.l64 = r.l_dev;
     I.g64 = r.g_dev;
     I.act = (int *)at(L.act);
+    I.cnt = (unsigned long long *)at(L.cnt);
     I.nblocks = r.dep_off.empty() ? 0u : (uint32_t)(r.dep_off.size() - 1);
     I.dep_off = (const uint32_t *)at(L.dep_off);
     I.dep = (const uint32_t *)at(L.dep);
@@ -930,7 +933,14 @@ public:
                 res.polish_iterations = st.n;
             }
             res.discounted_iterations = (r->phase == 0 && st.gamma != 1.0) ? st.n : st.n_disc;
-            res.node_updates = r->inst.act ? (int64_t)st.node_updates : (int64_t)st.epoch * (int64_t)r->npts;
+            res.node_updates = (int64_t)st.epoch * (int64_t)r->npts;
+            if (r->inst.act) {  // the per-block counts of computed grid points
+                std::vector<unsigned long long> c(r->inst.nblocks);
+                HJR_HIP(hipMemcpyAsync(c.data(), r->inst.cnt, c.size() * 8, hipMemcpyDeviceToHost, stream_));
+                HJR_HIP(hipStreamSynchronize(stream_));
+                res.node_updates = 0;
+                for (unsigned long long v : c) res.node_updates += (int64_t)v;
+            }
             res.intervals = st.intervals;
             res.t_final = st.t;
             res.last_delta = st.last_delta;

@@ -62,7 +62,6 @@ struct SolveState {
     long long n_disc;     // steps of the first phase taken with gamma < 1 (set at the anneal)
     int epoch;            // steps taken in all phases (local updates: the current step's number)
     int full_epoch;       // local updates: steps up to this epoch compute every block
-    unsigned long long node_updates;  // local updates: grid points of the steps computed so far
 };
 
 // Division by a runtime constant: q = (x * mul) >> (32 + shift), exact for 0 <= x < 2^31.
@@ -118,6 +117,7 @@ struct Inst {
     int *act;                // local updates (nullptr: off): two arrays of nblocks; act[e & 1][b]
                              // == e marks block b for step e
     uint32_t nblocks;        // node blocks of 2^kLocalShift nodes
+    unsigned long long *cnt; // per node block: grid points computed in all steps so far
     const uint32_t *dep_off; // per node block, its range in dep: the blocks within the reach of
     const uint32_t *dep;     // one full step's stencils (itself included)
     float *Vs32;             // interval-mode snapshot (FP32 phase)

@@ -209,8 +209,13 @@ __device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int st
             __syncthreads();  // red is rewritten by the next tile of a persistent grid
             const uint32_t span = (uint32_t)(NPT * kBlock);
             if (m > 0.0 || m != m) mark_dependents(I, st, start, span);
-            if (threadIdx.x == 0)
-                atomicAdd(&st->node_updates, (unsigned long long)(min(start + span, I.npts) - start));
+            // grid points computed, per block (one counter per block: no contention)
+            const uint32_t end = min(start + span, I.npts);
+            const uint32_t b = (start >> kLocalShift) + threadIdx.x;
+            if (b <= ((end - 1u) >> kLocalShift)) {
+                const uint32_t lo = max(start, b << kLocalShift), hi = min(end, (b + 1u) << kLocalShift);
+                atomicAdd(&I.cnt[b], (unsigned long long)(hi - lo));
+            }
         }
     }
 }
@@ -435,6 +440,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const Inst *__restrict__ i
         if (I.act && (node & ((1u << kLocalShift) - 1u)) == 0u) {  // local updates: no marks yet
             I.act[node >> kLocalShift] = -(1 << 30);
             I.act[I.nblocks + (node >> kLocalShift)] = -(1 << 30);
+            I.cnt[node >> kLocalShift] = 0ull;
         }
         if (fp32) {
             I.V32[node] = (float)v;
