@@ -368,3 +368,15 @@ def test_reach_avoid_weno_rk3_fixed_steps_and_device_entry(gpu, hjrlib, orc):
     rd, sd = hjrlib.solve_device(p.grid, p.dyn, lt, None, Vt, constraint=gt, precision=hjrlib.FP64, **opts)
     torch.cuda.synchronize()
     assert sd == st and np.array_equal(Vt.cpu().numpy().reshape(p.grid.shape), Vg)
+
+
+def test_discounted_weno_rk3_fixed_steps_match_oracle(gpu, hjrlib, orc):
+    """The discount in the TVD-RK3 step (it multiplies the third stage's combination): 120 FP64
+    WENO5 steps of the Dubins car with factor 0.95 match the oracle's."""
+    p = W.dubins_problem(25, dbar=0.1)
+    opts = dict(spatial=5, temporal=3, cfl=0.5, tol=1e-6, discount=0.95, max_iter=120)
+    Vo, io = orc.solve(p.grid, p.dyn, p.l, **opts)
+    assert io["steps"] == 120 and io["discounted_steps"] == 120
+    Vg, rg, st = hjrlib.solve(p.grid, p.dyn, p.l, None, precision=hjrlib.FP64, **opts)
+    assert st == hjrlib.NOT_CONVERGED and rg["iterations"] == 120 and rg["discounted_iterations"] == 120
+    assert np.abs(Vg - Vo).max() <= 1e-9 * np.abs(p.l).max()
