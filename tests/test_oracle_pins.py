@@ -723,3 +723,21 @@ def test_reach_avoid_brute_force_dynamic_programming(orc):
     assert err.max() < 0.04 and err.mean() < 2e-3
     assert ((Vo <= 0) != (Vs <= 0))[m].sum() <= 2
     assert ((gc > 0) & (pr.l < 0) & (Vo > 0)).any()  # where the obstacle covers the target it wins
+
+
+def test_discount_interval_mode_zero_flow_closed_form(orc):
+    """Interval mode (Sec. IV's rule) with a discount, no motion: dt = 1, so an interval of
+    length 3 is 3 steps and its change is gamma^(3(m-1)) (1 - gamma^3) max l; the first interval
+    whose change is below tol anneals the factor, and the next one (no change at all) stops."""
+    g = W.Grid((9, 10, 8), (-1.0, -1.0, -math.pi), (1.0, 1.0, math.pi), (False, False, True))
+    dyn = W.dubins3(0.0, 0.0, 0.0, 0.0)
+    l = W.smooth_field(g, seed=2)
+    lmax, tol, gamma = l.max(), 1e-6, 0.9
+    m = 1
+    while gamma ** (3 * (m - 1)) * (1 - gamma ** 3) * lmax >= tol:
+        m += 1
+    V, info = orc.solve(g, dyn, l, discount=gamma, tol=tol, spatial=orc.UPWIND1, temporal=orc.EULER,
+                        conv_mode=orc.CONV_INTERVAL, dt_report=3.0)
+    assert info["converged"] == 1
+    assert (info["intervals"], info["steps"], info["discounted_steps"]) == (m + 1, 3 * m + 3, 3 * m)
+    assert np.abs(V - np.where(l > 0, gamma ** (3 * m) * l, l)).max() <= 1e-13 * lmax
