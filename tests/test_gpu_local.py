@@ -72,7 +72,9 @@ def _periodic_di(n=41):
     dict(discount=0.9),
     dict(t_max=0.7, game=1),
     dict(precision=2, discount=0.95, conv_mode=1, dt_report=0.03),
-], ids=["plain", "interval", "discount", "horizon", "polish-discount-interval"])
+    dict(t_max=0.7, game=1, brs=1),
+    dict(precision=1, conv_mode=1, dt_report=0.05, game=1),
+], ids=["plain", "interval", "discount", "horizon", "polish-discount-interval", "reachable-set", "fp32-interval"])
 def test_euler_double_integrator_modes_bitwise(gpu, hjrlib, extra):
     """Euler ping-pong buffers, interval ends and horizon cuts (step size changes), the
     discount's anneal and the polish hand-over (full steps), on a 181^2 grid (32 blocks)."""
