@@ -198,6 +198,10 @@ typedef struct {
 
 /* Library information and defaults. */
 int32_t hjr_abi_version(void);
+/* Identity of this build: a hash of the library's sources and compiler flags, fixed at compile
+ * time (a NUL-terminated string owned by the library).  Lets a caller check that a prebuilt
+ * library matches the sources it was shipped with. */
+const char *hjr_build_id(void);
 hjr_status hjr_default_options(hjr_options *opts);
 const char *hjr_status_string(hjr_status status);
 const char *hjr_last_error(void);

@@ -71,8 +71,12 @@ def build(force: bool = False) -> str:
 def _load():
     global _lib
     if _lib is None:
-        build()
-        lib = C.CDLL(_LIB)
+        # HJR_ORACLE_LIBRARY: load another build of the oracle (a copy with a planted mistake,
+        # to check that the pins catch it); otherwise build this one if needed
+        alt = os.environ.get("HJR_ORACLE_LIBRARY")
+        if not alt:
+            build()
+        lib = C.CDLL(alt or _LIB)
         P = C.POINTER
         dp = P(C.c_double)
         lib.or_hamiltonian.argtypes = [P(_Dyn), C.c_int, dp, dp, dp, dp]

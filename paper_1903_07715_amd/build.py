@@ -34,6 +34,25 @@ def flags() -> list:
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
+def source_hash() -> str:
+    """Hash of everything the library is built from: every file under csrc/, the public header
+    and the compiler flags.  Compiled into the library (hjr_build_id) so a stale build can be
+    told from a current one."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        path = os.path.join(CSRC, name)
+        if os.path.isfile(path) and name.endswith((".hip", ".hpp", ".h")):
+            h.update(name.encode())
+            with open(path, "rb") as f:
+                h.update(f.read())
+    with open(os.path.join(ROOT, "include", "hjr.h"), "rb") as f:
+        h.update(f.read())
+    h.update(" ".join(flags()).replace(ROOT, "").encode())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str, obj: str, extra=()) -> None:
     cmd = [hipcc()] + flags() + list(extra) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -50,7 +69,7 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     objdir = os.path.join(HERE, "_build", os.path.basename(out))
     os.makedirs(objdir, exist_ok=True)
     objs = [os.path.join(objdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
-    extra = [f"-D{d}" for d in defines]
+    extra = [f"-D{d}" for d in defines] + [f'-DHJR_SOURCE_HASH="{source_hash()}"']
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         list(ex.map(lambda so: _compile(so[0], so[1], extra), zip(SOURCES, objs)))
     tmp = out + f".tmp{os.getpid()}"

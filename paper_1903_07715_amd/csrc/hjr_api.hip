@@ -1418,6 +1418,11 @@ extern "C" {
 
 int32_t hjr_abi_version(void) { return HJR_ABI_VERSION; }
 
+#ifndef HJR_SOURCE_HASH
+#define HJR_SOURCE_HASH "unknown"
+#endif
+const char *hjr_build_id(void) { return HJR_SOURCE_HASH; }
+
 hjr_status hjr_default_options(hjr_options *o)
 {
     if (!o) return fail(HJR_ERR_INVALID_ARG, "options must not be NULL");

@@ -26,7 +26,7 @@ EULER, TVDRK3 = 1, 3
 FP64, FP32, FP32_POLISH64 = 0, 1, 2
 CONV_PER_STEP, CONV_PER_INTERVAL = 0, 1
 
-EXPORTED = ["hjr_abi_version", "hjr_default_options", "hjr_status_string", "hjr_last_error",
+EXPORTED = ["hjr_abi_version", "hjr_build_id", "hjr_default_options", "hjr_status_string", "hjr_last_error",
             "hjr_device_count", "hjr_solve", "hjr_solve_device", "hjr_batch_solve", "hjr_cfl_dt",
             "hjr_stage_device", "hjr_ctx_create", "hjr_submit", "hjr_poll", "hjr_ctx_drain",
             "hjr_ctx_get_stats", "hjr_ctx_destroy", "hjr_profile_enable", "hjr_profile_read",
@@ -106,6 +106,7 @@ def load():
         vp = C.c_void_p
         dp = P(C.c_double)
         lib.hjr_abi_version.restype = C.c_int32
+        lib.hjr_build_id.restype = C.c_char_p
         lib.hjr_default_options.argtypes = [P(Options_)]
         lib.hjr_status_string.restype = C.c_char_p
         lib.hjr_status_string.argtypes = [C.c_int32]
@@ -135,7 +136,7 @@ def load():
         lib.hjr_safe_control_device.argtypes = [P(Grid_), P(Dynamics_), C.c_int32, vp, vp, C.c_int64, vp, vp, vp,
                                                 vp]
         for name in EXPORTED:
-            if name not in ("hjr_status_string", "hjr_last_error", "hjr_abi_version", "hjr_device_count",
+            if name not in ("hjr_status_string", "hjr_last_error", "hjr_abi_version", "hjr_build_id", "hjr_device_count",
                             "hjr_num_controls"):
                 getattr(lib, name).restype = C.c_int32
         _lib = lib
@@ -209,6 +210,11 @@ def abi_version() -> int:
     return int(load().hjr_abi_version())
 
 
+def build_id() -> str:
+    """The source hash compiled into the loaded library (see build.source_hash)."""
+    return load().hjr_build_id().decode()
+
+
 def device_count() -> int:
     return int(load().hjr_device_count())
 
@@ -233,6 +239,30 @@ def solve(grid, dyn, l: np.ndarray, k: Optional[np.ndarray] = None, constraint: 
     return V, result_dict(res), st
 
 
+def _device_array(t, name: str, numel: int, dtype: str = "float64", optional: bool = False):
+    """Check a torch tensor handed to a device entry point before anything is launched: the
+    element type, contiguity and element count the library will assume, and that it lives in
+    GPU memory.  Raises ValueError otherwise (a short or host array would make the kernels read
+    or write out of bounds)."""
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name}: a device array is required")
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != getattr(torch, dtype):
+        raise ValueError(f"{name}: dtype {t.dtype}, expected torch.{dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: the tensor must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name}: {t.numel()} elements, expected {numel}")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: the tensor must be in GPU memory")
+    return t
+
+
 def _tptr(t) -> Optional[int]:
     return None if t is None else int(t.data_ptr())
 
@@ -246,9 +276,11 @@ def _stream_ptr(stream) -> Optional[int]:
 def solve_device(grid, dyn, l_dev, k_dev, V_dev, stream=None, constraint=None, **opts):
     """hjr_solve_device on torch FP64 device tensors (hjr_solve_reach_avoid_device when a
     constraint function g is given as a device tensor).  Returns (result dict, status)."""
-    for t in (l_dev, k_dev, V_dev, constraint):
-        if t is not None and (not t.is_cuda or t.dtype.itemsize != 8 or not t.is_contiguous()):
-            raise ValueError("device arrays must be contiguous FP64 GPU tensors")
+    n = grid.size
+    _device_array(l_dev, "l", n)
+    _device_array(k_dev, "k", n, optional=True)
+    _device_array(V_dev, "V", n)
+    _device_array(constraint, "constraint", n, optional=True)
     res = Result_()
     o = options(**opts)
     gs, ds = C.byref(grid_struct(grid)), C.byref(dyn_struct(dyn))
@@ -309,6 +341,9 @@ def stage_device(grid, dyn, stage, dt, Vs, Vn, l, out, game=AVOID, spatial=WENO5
                  precision=FP64, stream=None):
     """One integrator stage with the solver's own kernel (torch device tensors of the precision's
     element type).  Returns max |out - Vn| for the step's last stage, else None."""
+    dt_name = "float32" if precision == FP32 else "float64"
+    for t, name in ((Vs, "Vs"), (Vn, "Vn"), (l, "l"), (out, "out")):
+        _device_array(t, name, grid.size, dt_name)
     delta = C.c_double(float("nan"))
     st = load().hjr_stage_device(C.byref(grid_struct(grid)), C.byref(dyn_struct(dyn)), game, spatial, temporal,
                                  stage, precision, dt, _tptr(Vs), _tptr(Vn), _tptr(l), _tptr(out),
@@ -322,31 +357,26 @@ def num_controls(dyn) -> int:
     return int(load().hjr_num_controls(dyn.id))
 
 
-def _check_f64_dev(*ts):
-    for t in ts:
-        if t is not None and (not t.is_cuda or t.dtype.itemsize != 8 or not t.is_contiguous()):
-            raise ValueError("device arrays must be contiguous FP64 GPU tensors")
-
-
 def gradient_device(grid, V, table, spatial=WENO5, stream=None) -> None:
     """hjr_gradient_device: query table (npts x (ndim + 1): gradient components, then V) of V."""
-    _check_f64_dev(V, table)
-    if V.numel() != grid.size or table.numel() != (grid.ndim + 1) * grid.size:
-        raise ValueError("array sizes do not match the grid")
+    _device_array(V, "V", grid.size)
+    _device_array(table, "table", (grid.ndim + 1) * grid.size)
     _check(load().hjr_gradient_device(C.byref(grid_struct(grid)), spatial, _tptr(V), _tptr(table),
                                       _stream_ptr(stream)))
 
 
 def safe_control_device(grid, dyn, table, x, u, p=None, v=None, game=AVOID, stream=None) -> None:
     """hjr_safe_control_device on device tensors: x (nq x ndim) -> u (nq x nu), optional p, v."""
-    _check_f64_dev(table, x, u, p, v)
+    import torch
+
+    if not isinstance(x, torch.Tensor):
+        raise ValueError("x: expected a torch tensor")
     nq = x.shape[0] if x.dim() > 1 else x.numel() // grid.ndim
-    if x.numel() != nq * grid.ndim or u.numel() != nq * num_controls(dyn):
-        raise ValueError("query array sizes do not match")
-    if table.numel() != (grid.ndim + 1) * grid.size:
-        raise ValueError("the table does not match the grid")
-    if (p is not None and p.numel() != nq * grid.ndim) or (v is not None and v.numel() != nq):
-        raise ValueError("output array sizes do not match")
+    _device_array(table, "table", (grid.ndim + 1) * grid.size)
+    _device_array(x, "x", nq * grid.ndim)
+    _device_array(u, "u", nq * num_controls(dyn))
+    _device_array(p, "p", nq * grid.ndim, optional=True)
+    _device_array(v, "v", nq, optional=True)
     _check(load().hjr_safe_control_device(C.byref(grid_struct(grid)), C.byref(dyn_struct(dyn)), game, _tptr(table),
                                           _tptr(x), nq, _tptr(u), _tptr(p), _tptr(v), _stream_ptr(stream)))
 
@@ -376,6 +406,10 @@ class Context:
         self._keep = {}
 
     def submit(self, grid, dyn, l_dev, k_dev, V_dev, **opts) -> int:
+        n = grid.size
+        _device_array(l_dev, "l", n)
+        _device_array(k_dev, "k", n, optional=True)
+        _device_array(V_dev, "V", n)
         t = C.c_int64()
         o = options(**opts)
         _check(load().hjr_submit(self._h, C.byref(grid_struct(grid)), C.byref(dyn_struct(dyn)), _tptr(l_dev),

@@ -9,6 +9,11 @@ request of the same kind, preferring one whose problem dominates the new one (mo
 authority, less disturbance, a smaller target).  By Theorem 2 and Propositions 1-2 a dominating
 warm start converges to the new problem's value function exactly; any other warm start is still
 conservative by Theorem 1.
+
+Only converged results (status OK) are kept as warm starts: Theorem 2's exactness assumes the
+prior is the converged value function of its problem.  Every request records whether its warm
+start came from a dominating prior (``exact_warm``: exact by Theorem 2) or not (conservative
+only); with ``only_dominating=True`` requests without a dominating prior start cold instead.
 """
 from __future__ import annotations
 
@@ -36,32 +41,37 @@ class Request:
     status: int = 0
     result: dict = field(default_factory=dict)
     warm_from: Optional[tuple] = None
+    exact_warm: Optional[bool] = None   # None: cold; True: dominating prior; False: any other prior
     V: object = None
 
 
 class WarmStartServer:
     """Drive an hjr.Context with a request stream; keep solutions resident as warm starts."""
 
-    def __init__(self, ctx: "hjr.Context", warm: bool = True, resident_per_kind: int = 8):
+    def __init__(self, ctx: "hjr.Context", warm: bool = True, resident_per_kind: int = 8,
+                 only_dominating: bool = False):
         self.ctx = ctx
         self.warm = warm
+        self.only_dominating = only_dominating
         self.resident_per_kind = resident_per_kind
         self.resident = {}     # kind -> list of (key, V tensor, last use)
 
     def pick_warm_start(self, req: Request):
+        """(k, prior key, exact): the nearest resident prior of the request's kind, preferring
+        dominating ones (exact = True); (None, None, None) for a cold start."""
         if not self.warm:
-            return None, None
+            return None, None, None
         cands = self.resident.get(req.kind, [])
-        if not cands:
-            return None, None
 
         def dist(a, b):
             return math.sqrt(sum((x - y) ** 2 for x, y in zip(a, b)))
         dom = [c for c in cands if req.dominates(c[0], req.key)]
-        pool = dom if dom else cands
+        pool = dom if dom else ([] if self.only_dominating else cands)
+        if not pool:
+            return None, None, None
         best = min(pool, key=lambda c: dist(c[0], req.key))
         best[2] = time.perf_counter()
-        return best[1], best[0]
+        return best[1], best[0], bool(dom)
 
     def keep(self, req: Request):
         lst = self.resident.setdefault(req.kind, [])
@@ -80,8 +90,9 @@ class WarmStartServer:
             now = time.perf_counter() - t0
             while i < len(pending) and pending[i].arrival <= now:
                 r = pending[i]
-                k, key = self.pick_warm_start(r)
+                k, key, exact = self.pick_warm_start(r)
                 r.warm_from = key
+                r.exact_warm = exact
                 r.V = torch.empty_like(r.l_dev)
                 r.submitted = time.perf_counter() - t0
                 r.ticket = self.ctx.submit(r.grid, r.dyn, r.l_dev, k, r.V, **r.opts)
@@ -94,13 +105,15 @@ class WarmStartServer:
                 r = active.pop(t)
                 r.status, r.result = res
                 r.done = time.perf_counter() - t0
-                if r.status >= 0:
+                if r.status == hjr.OK:
                     self.keep(r)
             time.sleep(poll_interval)
         return requests
 
 
 def latency_stats(requests):
+    """Latency percentiles over all requests; solves/s counts converged results only (status OK),
+    and the others are reported apart."""
     lat = sorted(r.done - r.arrival for r in requests)
 
     def pct(q):
@@ -108,5 +121,6 @@ def latency_stats(requests):
             return float("nan")
         return lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)]
     span = max(r.done for r in requests) - min(r.arrival for r in requests)
-    return {"requests": len(requests), "seconds": span, "solves_per_s": len(requests) / span,
-            "p50_s": pct(0.50), "p99_s": pct(0.99), "mean_s": sum(lat) / len(lat)}
+    ok = sum(1 for r in requests if r.status == hjr.OK)
+    return {"requests": len(requests), "converged": ok, "not_converged": len(requests) - ok, "seconds": span,
+            "solves_per_s": ok / span, "p50_s": pct(0.50), "p99_s": pct(0.99), "mean_s": sum(lat) / len(lat)}

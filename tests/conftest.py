@@ -23,12 +23,18 @@ def orc():
 
 @pytest.fixture(scope="session")
 def hjrlib():
-    """The HIP library, built in-tree if it is not there yet (hipcc cross-compiles on a CPU host)."""
+    """The HIP library, built in-tree if it is not there yet (hipcc cross-compiles on a CPU host).
+    A library built from other sources than the ones in the tree is rejected: its results would
+    not be those of the code under test."""
     from paper_1903_07715_amd import build, hjr
 
     if not os.path.exists(hjr.LIB_PATH):
         build.build()
     hjr.load()
+    want = build.source_hash()
+    if hjr.build_id() != want:
+        pytest.fail(f"{hjr.LIB_PATH} was built from other sources (build id {hjr.build_id()}, sources "
+                    f"{want}); rebuild it with `python -m paper_1903_07715_amd.build`")
     return hjr
 
 

@@ -741,3 +741,167 @@ def test_discount_interval_mode_zero_flow_closed_form(orc):
     assert info["converged"] == 1
     assert (info["intervals"], info["steps"], info["discounted_steps"]) == (m + 1, 3 * m + 3, 3 * m)
     assert np.abs(V - np.where(l > 0, gamma ** (3 * m) * l, l)).max() <= 1e-13 * lmax
+
+
+# ---------------------------------------------------------------------------------------------
+# The 6-D quadrotor by axis (its dynamics split into three independent (p_i, v_i) games)
+# ---------------------------------------------------------------------------------------------
+
+def _quad_axis_grid(ax, n):
+    """A 6-D grid with n nodes on axis ax's position and velocity dims and 3 on the others."""
+    nn = [3] * 6
+    nn[ax] = n
+    nn[ax + 3] = n
+    return W.Grid(tuple(nn), (-5, -5, -5, -3, -3, -3), (5, 5, 5, 3, 3, 3))
+
+
+@pytest.mark.parametrize("ax", [0, 1, 2], ids=["x", "y", "z"])
+def test_quad6_axis_equals_its_planar_model(orc, ax):
+    """With a target that depends on one position coordinate only (a slab |p_i| <= 1) and no
+    disturbance, the 6-D value function is constant along the other axes, and on axis i the
+    Hamiltonian, the dissipation coefficients and the grid are those of a planar model: the
+    double integrator with control bound g tan(theta_max) (x) or g tan(phi_max) (y), and the
+    vertical model p' = v, v' = T/m - g with T in [T_min, T_max] (z).  Each has its own code in
+    the oracle, so the 6-D indexing, strides and per-axis coefficients must reproduce the planar
+    fixed point node for node (the Euler fixed point does not depend on dt).  The two angle
+    bounds differ, so a swapped pair fails."""
+    q = W.quad6(m=1.2, dbar=(0.0, 0.0, 0.0), phi_max=0.2, theta_max=0.3)
+    g6 = _quad_axis_grid(ax, 21)
+    l6 = np.ascontiguousarray(np.broadcast_to(np.abs(g6.mesh()[ax]) - 1.0, g6.shape))
+    V6, i6 = orc.solve(g6, q, l6, spatial=orc.UPWIND1, temporal=orc.EULER, cfl=0.8, tol=1e-12, max_iter=50000)
+    g2 = W.Grid((21, 21), (g6.lo[ax], g6.lo[ax + 3]), (g6.hi[ax], g6.hi[ax + 3]))
+    if ax < 2:
+        dyn = W.double_integrator(9.81 * math.tan(0.3 if ax == 0 else 0.2), 1.0, 0.0)
+    else:
+        dyn = W.quad10_z(m=1.2, dbar=0.0, kt=1.0, tmin=5.0, tmax=20.0)
+    l2 = np.ascontiguousarray(np.broadcast_to(np.abs(g2.mesh()[0]) - 1.0, g2.shape))
+    V2, i2 = orc.solve(g2, dyn, l2, spatial=orc.UPWIND1, temporal=orc.EULER, cfl=0.8, tol=1e-12, max_iter=50000)
+    assert i6["converged"] == 1 and i2["converged"] == 1
+    shp = [1] * 6
+    shp[ax] = shp[ax + 3] = 21
+    assert np.abs(V6 - V2.reshape(shp)).max() < 1e-9
+    assert np.abs(V2 - l2).max() > 0.5  # the solve really moved
+
+
+def _slab_vstar(P, Vv, h, a_pos, a_neg):
+    """Slab |p| <= h to stay out of, p' = v, v' = a with the braking deceleration net of the
+    disturbance a_pos (p > 0 moving down) or a_neg (p < 0 moving up): the closest approach of
+    |p| to 0 is p - v^2 / (2 a) when moving toward the slab, else p itself; crossing p = 0
+    means reaching 0."""
+    up = np.maximum(P - np.maximum(0.0, -Vv) ** 2 / (2 * a_pos), 0.0)
+    dn = np.maximum(-P - np.maximum(0.0, Vv) ** 2 / (2 * a_neg), 0.0)
+    return np.where(P >= 0, up, dn) - h
+
+
+@pytest.mark.parametrize("ax", [0, 1, 2], ids=["x", "y", "z"])
+def test_quad6_axis_braking_closed_form_with_disturbance(orc, ax):
+    """The 6-D quadrotor with a disturbance on every acceleration, target slab |p_i| <= 1 on one
+    axis: V* is the braking closed form with the control's deceleration net of the disturbance,
+    g tan(theta_max) - d_x, g tan(phi_max) - d_y, and T_max/m - g - d_z upward or
+    g - T_min/m - d_z downward (the thrust interval is not symmetric).  First order: the mean
+    error away from the kinks of V* halves with the spacing."""
+    G = 9.81
+    db = (0.5, 0.4, 0.6)
+    q = W.quad6(m=1.2, dbar=db, phi_max=0.2, theta_max=0.3)
+    acc = [(G * math.tan(0.3) - db[0],) * 2, (G * math.tan(0.2) - db[1],) * 2,
+           (20.0 / 1.2 - G - db[2], G - 5.0 / 1.2 - db[2])][ax]
+    means = []
+    for n in (21, 31):
+        g6 = _quad_axis_grid(ax, n)
+        P, Vv = g6.mesh()[ax], g6.mesh()[ax + 3]
+        l6 = np.ascontiguousarray(np.broadcast_to(np.abs(P) - 1.0, g6.shape))
+        V6, info = orc.solve(g6, q, l6, spatial=orc.UPWIND1, temporal=orc.EULER, cfl=0.8, tol=1e-8, max_iter=50000)
+        assert info["converged"] == 1
+        ex = np.broadcast_to(_slab_vstar(P, Vv, 1.0, *acc), g6.shape)
+        reach = np.where(P >= 0, P - np.maximum(0.0, -Vv) ** 2 / (2 * acc[0]),
+                         -P - np.maximum(0.0, Vv) ** 2 / (2 * acc[1]))
+        dx = g6.spacing(ax)
+        mask = np.broadcast_to((np.abs(P) <= 4.0) & (np.abs(Vv) <= 2.5) & (np.abs(P) > 2 * dx)
+                               & (np.abs(reach) > 2 * dx), g6.shape)
+        err = np.abs(V6 - ex)[mask]
+        assert err.max() < 0.3
+        means.append(err.mean())
+    assert means[1] < 0.045
+    assert means[0] / means[1] > 1.3  # first order: 21 -> 31 nodes shrinks the spacing by 1.5
+
+
+# ---------------------------------------------------------------------------------------------
+# The 4-D unicycle with the disturbance as the only input: the tube in closed form
+# ---------------------------------------------------------------------------------------------
+
+def _unicycle_tube(g, centers, radii, dbar, T, box, nt=2001):
+    """No control: the position after time t is x + v t (cos th, sin th) plus any point of the
+    disturbance's reachable set, the disk (ball) or square (box) of radius dbar t, so the worst
+    case of l at time t is the distance from each obstacle centre to that set minus the radius;
+    the tube value is its minimum over t in [0, T] (sampled densely; Lipschitz in t)."""
+    X, Y, TH, VV = g.mesh()
+    out = np.full(g.shape, np.inf)
+    for t in np.linspace(0.0, T, nt):
+        qx = X + VV * t * np.cos(TH)
+        qy = Y + VV * t * np.sin(TH)
+        for c, r in zip(centers, radii):
+            if box:
+                dist = np.hypot(np.maximum(np.abs(qx - c[0]) - dbar * t, 0.0),
+                                np.maximum(np.abs(qy - c[1]) - dbar * t, 0.0))
+            else:
+                dist = np.maximum(np.hypot(qx - c[0], qy - c[1]) - dbar * t, 0.0)
+            out = np.minimum(out, dist - r)
+    return out
+
+
+@pytest.mark.parametrize("box", [False, True], ids=["ball", "box"])
+def test_unicycle_disturbance_only_tube_closed_form(orc, box):
+    """4-D unicycle (x, y, heading, speed) with no control (the speed stays put, the heading too)
+    and |d| <= 0.3 in the Euclidean ball or the box, two seeded disk obstacles, horizon T = 2:
+    WENO5 + TVD-RK3 against the closed form above.  The other shape's closed form differs by
+    0.09 on average, ten times the tolerance, so a mistake in the disturbance term fails."""
+    centers, radii, _ = W.unicycle_centers()
+    g = W.Grid((31, 31, 24, 7), (-5, -5, -math.pi, 0.0), (5, 5, math.pi, 2.0), (False, False, True, False))
+    l = W.disks_sdf(g, centers, radii)
+    dyn = W.unicycle4(0.0, 0.0, 0.3, box=box)
+    V, info = orc.solve(g, dyn, l, spatial=orc.WENO5, temporal=orc.RK3, cfl=0.5, tol=1e-300, t_max=2.0,
+                        max_iter=100000)
+    assert info["converged"] == 2 and abs(info["t"] - 2.0) < 1e-9
+    ex = _unicycle_tube(g, centers, radii, 0.3, 2.0, box)
+    other = _unicycle_tube(g, centers, radii, 0.3, 2.0, not box)
+    err = np.abs(V - ex)
+    assert err.mean() < 0.015
+    assert np.percentile(err, 90) < 0.05          # the other shape: 0.24
+    assert np.abs(other - ex).mean() > 6 * err.mean()
+    assert np.percentile(np.abs(other - ex), 90) > 4 * np.percentile(err, 90)
+    # at speed 0 only the disturbance moves the car
+    assert err[..., 0].mean() < 0.01
+
+
+# ---------------------------------------------------------------------------------------------
+# Remark 1 (appendix): the target shrinks
+# ---------------------------------------------------------------------------------------------
+
+def test_remark1_target_shrinks_bounds_every_iterate(orc):
+    """Remark 1: warm-starting the smaller target's computation from the converged value
+    function of a larger target gives k <= V_k(., t) <= V*_new at every t.  For the monotone
+    scheme (upwind + Lax-Friedrichs + Euler at CFL <= 1, no boundary) this holds for every
+    iterate: k is a fixed point of the old step and the new step only raises the projection
+    bound (l_new >= l_old), so the iterates rise monotonically and stay below the new fixed
+    point.  The iterates also reach V*_new."""
+    g = W.Grid((41, 41), (-1, -1), (1, 1), (True, True))
+    dyn = W.double_integrator(1.0, 1.0, 0.1)
+    l_old = W.box_sdf(g, (0, 0), (0.3, 0.3))
+    l_new = W.box_sdf(g, (0, 0), (0.2, 0.2))
+    assert np.all(l_old <= l_new) and np.any(l_old < l_new)
+    opts = dict(spatial=orc.UPWIND1, temporal=orc.EULER, cfl=0.8, tol=1e-12, max_iter=50000)
+    k, _ = orc.solve(g, dyn, l_old, **opts)
+    Vnew, info = orc.solve(g, dyn, l_new, **opts)
+    assert info["converged"] == 1 and (k - Vnew).max() <= 0 and (Vnew - k).max() > 0.05
+    dt = orc.cfl_dt(g, dyn, 0.8)
+    V = np.minimum(k, l_new)
+    assert np.array_equal(V, k)
+    prev = V
+    for _ in range(400):
+        V, _ = orc.step(g, dyn, V, l_new, dt, spatial=orc.UPWIND1, temporal=orc.EULER)
+        assert (k - V).max() <= 1e-13          # k <= V_k
+        assert (V - Vnew).max() <= 1e-10       # V_k <= V*_new
+        assert (prev - V).max() <= 1e-13       # monotone rise
+        prev = V
+    Vw, iw = orc.solve(g, dyn, l_new, k, **opts)
+    assert iw["converged"] == 1 and np.abs(Vw - Vnew).max() < 1e-8
