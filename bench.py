@@ -1,12 +1,14 @@
 """Benchmark: warm-started HJI reachability solves on one MI355X.
 
-One benchmark step is one complete warm-started solve of the 3-D Dubins car on a 101^3 grid
-([-5,5]^2 x [-pi,pi), heading periodic): WENO5 + TVD-RK3 at CFL 0.5 in FP32 until the max-norm
-change is below the FP32 threshold, then the FP64 polish to 1e-6.  The warm start k is the
-solution with the disturbance bound halved (0.05 -> 0.1; exact by Theorem 2).  Inputs (l, k) are
-resident in device memory before the timed region starts.
+One benchmark step is one complete warm-started solve of the 6-D quadrotor (translational
+dynamics, thrust and two tilt angles as controls, a disturbance on every acceleration) on a 25^6
+grid (244 M nodes, p in [-5,5]^3, v in [-3,3]^3, a cube obstacle |p_i| <= 1): first-order upwind +
+Lax-Friedrichs + forward Euler at CFL 0.8 in FP32 until the max-norm change is below the FP32
+threshold, then the FP64 polish to 1e-6.  The warm start k is the solution with the smaller
+disturbance bound 0.3 (the new problem has 0.5; exact by Theorem 2).  Inputs (l, k) are resident
+in device memory before the timed region starts.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload quad6|dubins|...]
 
 Prints one JSON line.  `value` is grid-point updates per second over the timed solves (every
 node advanced one full time step, FP32 and FP64 steps alike).
@@ -33,6 +35,9 @@ FLOP_PER_NODE_STAGE_DUBINS_WENO5 = 3 * 184 + 20 + 6 + 5          # = 583
 # Algorithmic HBM bytes per node per RK3 step in FP32 (no halo re-reads): stage 1 reads V, writes
 # V1 (8); stage 2 reads V1, V, writes V2 (12); stage 3 reads V2, V, l, writes V (16).
 BYTES_PER_NODE_STEP_RK3_FP32 = 36
+# One forward-Euler step reads V and l and writes V: 12 bytes per node in FP32, 24 in FP64.
+BYTES_PER_NODE_STEP_EULER_FP32 = 12
+BYTES_PER_NODE_STEP_EULER_FP64 = 24
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (packed FMA) peak
 PEAK_HBM_GBS = 8000.0
@@ -66,10 +71,12 @@ def parse():
     ap.add_argument("--polish-shift", type=float, default=-1.0, help="FP64 polish start shift (< 0: automatic)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["dubins", "batch", "serve", "control", "quad10", "hbm", "discount",
-                                           "local"],
-                    default="dubins",
-                    help="dubins: the headline single-solve benchmark; batch: the 64-instance mixed batch; "
+    ap.add_argument("--workload", choices=["quad6", "dubins", "batch", "serve", "control", "quad10", "hbm",
+                                           "discount", "local"],
+                    default="quad6",
+                    help="quad6: the headline, warm-started FP32 + FP64-polish solves of the 25^6 quadrotor; "
+                         "dubins: warm-started solves of the 101^3 Dubins car (WENO5 + TVD-RK3); "
+                         "batch: the 64-instance mixed batch; "
                          "serve: a Poisson request stream through the serving context, warm vs cold; "
                          "control: safe-control queries against the converged 101^3 Dubins value function; "
                          "quad10: the 10-D near-hover quadrotor scenario of Sec. VI by subsystem, warm vs cold; "
@@ -81,7 +88,9 @@ def parse():
                     help="discount: per-step factor, annealed to 1 (default: Table 1's 0.999)")
     ap.add_argument("--queries", type=int, default=1 << 20, help="control: query states per batch")
     ap.add_argument("--requests", type=int, default=32, help="serve: number of requests")
-    ap.add_argument("--quad-n", type=int, default=25, help="serve: grid side of the 6-D quadrotor requests")
+    ap.add_argument("--quad-n", type=int, default=25, help="quad6, hbm, serve: grid side of the 6-D quadrotor")
+    ap.add_argument("--parity-n", type=int, default=9,
+                    help="quad6: grid side of the reduced solve the CPU-baseline leg also checks against")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run 5 plain device copies of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -150,6 +159,187 @@ def main():
     if args.workload == "serve":
         bench_serve(args)
         return
+    if args.workload == "quad6":
+        return bench_quad6(args)
+    return bench_dubins(args)
+
+
+def working_avg(entries):
+    """Average event-timed duration (s) of the working launches (steps some instance was still
+    taking; launches issued after convergence return at once and are left out)."""
+    n = sum(e["working_launches"] for e in entries)
+    ms = sum(e["working_ms"] for e in entries)
+    return (ms / n / 1e3 if n else float("nan")), n
+
+
+def cpu_baseline_quad6(p, q, n_par, gpu_solve):
+    """The FP64 oracle, as it stands, on the host: the same warm-started problem on a reduced
+    n^6 grid (its prior solve, then the warm-started solve, which is timed).  The GPU solves the
+    same reduced problem from the oracle's prior, and the two results are compared: max |V - V_oracle|
+    and the nodes whose sign differs where |V_oracle| > 1e-4 max|l|."""
+    import numpy as np
+
+    import oracle
+    from paper_1903_07715_amd import workloads as W
+
+    pr = W.quad6_problem(n_par, m=p.dyn.params[1], dbar=p.dyn.params[6:9])
+    qr = W.quad6_problem(n_par, m=q.dyn.params[1], dbar=q.dyn.params[6:9])
+    opts = oracle.problem_opts(pr)
+    t0 = time.perf_counter()
+    K, ik = oracle.solve(qr.grid, qr.dyn, qr.l, **opts)
+    t1 = time.perf_counter()
+    log(f"  oracle prior {n_par}^6: {ik['steps']} steps, {t1 - t0:.1f} s")
+    V, iv = oracle.solve(pr.grid, pr.dyn, pr.l, K, **opts)
+    t2 = time.perf_counter()
+    log(f"  oracle warm {n_par}^6: {iv['steps']} steps, {t2 - t1:.1f} s")
+    Vg, st, res = gpu_solve(pr, K)
+    band = 1e-4 * float(np.abs(pr.l).max())
+    err = float(np.abs(Vg - V).max())
+    mism = int(np.sum(((Vg <= 0) != (V <= 0)) & (np.abs(V) > band)))
+    base = {"value": iv["steps"] * pr.grid.size / (t2 - t1), "unit": "grid-point updates/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"the warm-started solve of the same problem on a {n_par}^6 grid ({iv['steps']} FP64 "
+                      f"upwind + Euler steps, {t2 - t1:.1f} s; its prior solve took {t1 - t0:.1f} s more)"}
+    parity = {"grid": [n_par] * 6, "max_abs_err": err, "band": band, "err_over_band": err / band,
+              "sign_mismatches_off_band": mism, "gpu_status": st,
+              "gpu_steps": [res["iterations"], res["polish_iterations"]], "oracle_steps": iv["steps"]}
+    return base, parity
+
+
+def bench_quad6(args):
+    """The headline: warm-started FP32 + FP64-polish solves of the 6-D quadrotor on a 25^6 grid."""
+    import numpy as np
+    import torch
+
+    from paper_1903_07715_amd import hjr
+    from paper_1903_07715_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    n = args.quad_n
+    p = W.quad6_problem(n, m=1.2, dbar=(0.5, 0.5, 0.5))
+    q = W.quad6_problem(n, m=1.2, dbar=(0.3, 0.3, 0.3))
+    npts = p.grid.size
+    opts = hjr.problem_options(p, precision=hjr.FP32_POLISH64, max_iter=20000, polish_shift=args.polish_shift)
+    stream = torch.cuda.Stream()
+    l_t = torch.tensor(p.l, device=dev)
+    k_t = torch.empty_like(l_t)
+    V_t = torch.empty_like(l_t)
+    log(f"quad6 {n}^6 = {npts} nodes; warm-start function: the solution with disturbance 0.3")
+    rq, sq = hjr.solve_device(q.grid, q.dyn, l_t, None, k_t, stream=stream, **opts)
+    torch.cuda.synchronize()
+    log(f"  prior: {rq['iterations']}+{rq['polish_iterations']} steps, status {sq}, {rq['seconds']:.3f} s")
+
+    def run(warm: bool):
+        return hjr.solve_device(p.grid, p.dyn, l_t, k_t if warm else None, V_t, stream=stream, **opts)
+
+    for i in range(args.warmup):
+        r, st = run(True)
+        log(f"warmup {i}: {r['iterations']}+{r['polish_iterations']} steps, status {st}, {r['seconds']:.3f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    updates = 0
+    statuses = []
+    res = None
+    for i in range(args.steps):
+        res, st = run(True)
+        statuses.append(st)
+        updates += (res["iterations"] + res["polish_iterations"]) * npts
+        log(f"timed warm solve {i}: {res['iterations']}+{res['polish_iterations']} steps, status {st}")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+
+    # the same solves with launch-stamped events around every stage kernel (kept out of `value`)
+    hjr.profile_read(reset=True)
+    hjr.profile_enable(True)
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for i in range(args.steps):
+        run(True)
+    torch.cuda.synchronize()
+    pel = time.perf_counter() - p0
+    hjr.profile_enable(False)
+    prof = hjr.profile_read(reset=True)
+    log(f"event-timed pass: {pel:.3f} s vs {el:.3f} s untimed")
+
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    cres = None
+    cstat = []
+    for i in range(args.steps):
+        cres, cst = run(False)
+        cstat.append(cst)
+        log(f"cold solve {i}: {cres['iterations']}+{cres['polish_iterations']} steps, status {cst}")
+    torch.cuda.synchronize()
+    cel = time.perf_counter() - c0
+
+    # one warm solve through the host-array entry point (l and k in over PCIe, V back)
+    l_h = p.l
+    k_h = k_t.cpu().numpy().reshape(p.grid.shape)
+    h0 = time.perf_counter()
+    hjr.solve(p.grid, p.dyn, l_h, k_h, **opts)
+    hel = time.perf_counter() - h0
+    log(f"host-array warm solve: {hel:.3f} s")
+    del k_h
+
+    avg32, n32 = working_avg(prof["stage32"])
+    avg64, n64 = working_avg(prof["stage64"])
+    gbs32 = BYTES_PER_NODE_STEP_EULER_FP32 * npts / avg32 / 1e9
+    gbs64 = BYTES_PER_NODE_STEP_EULER_FP64 * npts / avg64 / 1e9
+    roofline = {"bound": "hbm", "achieved": round(gbs32, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs32 / PEAK_HBM_GBS, 4), "traffic": MEASURED_TRAFFIC.get(kernel_source_hash()),
+                "kernel": "march_kernel<float, Quad6> (upwind + Lax-Friedrichs + Euler step, FP32)",
+                "bytes_per_update": BYTES_PER_NODE_STEP_EULER_FP32,
+                "avg_launch_us": round(avg32 * 1e6, 1), "working_launches": n32,
+                "fp64_polish_kernel": {"achieved": round(gbs64, 1), "frac": round(gbs64 / PEAK_HBM_GBS, 4),
+                                       "bytes_per_update": BYTES_PER_NODE_STEP_EULER_FP64,
+                                       "avg_launch_us": round(avg64 * 1e6, 1), "working_launches": n64}}
+    line = {
+        "metric": "grid-point updates/s (%HBM peak); warm vs cold solves/s, p50/p99 latency",
+        "value": updates / el,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"quad6-{n}^6-upwind-euler-fp32-polish64-warm", "grid": [n] * 6, "points": npts,
+                   "cfl": p.cfl, "tol": p.tol, "mass": 1.2, "dbar": 0.5, "prior_dbar": 0.3},
+        "ms_per_solve": el / args.steps * 1e3,
+        "warm_solves_per_s": args.steps / el,
+        "cold_solves_per_s": args.steps / cel,
+        "warm_over_cold": cel / el,
+        "warm_iterations": [res["iterations"], res["polish_iterations"]],
+        "cold_iterations": [cres["iterations"], cres["polish_iterations"]],
+        "statuses_warm": statuses,
+        "statuses_cold": cstat,
+        "host_io_warm_solves_per_s": 1.0 / hel,
+        "event_pass_seconds": pel,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) and reduced-grid parity")
+
+        def gpu_solve(pr, K):
+            lt = torch.tensor(pr.l, device=dev)
+            kt = torch.tensor(K, device=dev)
+            Vt = torch.empty_like(lt)
+            r, st = hjr.solve_device(pr.grid, pr.dyn, lt, kt, Vt, **hjr.problem_options(
+                pr, precision=hjr.FP32_POLISH64, max_iter=20000))
+            torch.cuda.synchronize()
+            return Vt.cpu().numpy().reshape(pr.grid.shape), st, r
+
+        line["cpu_baseline"], line["parity"] = cpu_baseline_quad6(p, q, args.parity_n, gpu_solve)
+    print(json.dumps(line), flush=True)
+
+
+def bench_dubins(args):
     import torch
 
     from paper_1903_07715_amd import hjr
@@ -231,17 +421,14 @@ def main():
     hel = time.perf_counter() - h0
     log(f"host-array warm solves: {hel / args.steps * 1e3:.1f} ms each")
 
-    s32 = prof["stage32"]
-    launches = sum(s["launches"] for s in s32)
-    kms = sum(s["ms"] for s in s32)
-    avg_s = kms / launches / 1e3 if launches else float("nan")
+    avg_s, launches = working_avg(prof["stage32"])
     flops = FLOP_PER_NODE_STAGE_DUBINS_WENO5 * npts
     achieved_tflops = flops / avg_s / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
                 "traffic": MEASURED_TRAFFIC.get(kernel_source_hash()),
                 "kernel": "stage_kernel_one<float, Dubins, WENO5> (WENO5 + LF + TVD-RK3 stage)",
-                "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+                "avg_launch_us": round(avg_s * 1e6, 2), "working_launches": launches,
                 "algorithmic_gbs": round(BYTES_PER_NODE_STEP_RK3_FP32 / 3 * npts / avg_s / 1e9, 1)}
     line = {
         "metric": "grid-point updates/s (warm-started solve)",
@@ -528,8 +715,7 @@ def bench_hbm(args):
     el = time.perf_counter() - t0
     hjr.profile_enable(False)
     prof = hjr.profile_read(reset=True)
-    k = prof["stage32"][0]
-    avg_s = k["ms"] / k["launches"] / 1e3
+    avg_s, nwork = working_avg(prof["stage32"])
     gbs = 12.0 * npts / avg_s / 1e9
     log(f"stage kernel {avg_s * 1e6:.1f} us per launch, {gbs:.0f} GB/s algorithmic")
     print(json.dumps({"workload": f"quad6-{args.quad_n}^6-upwind-euler-fp32", "nodes": npts,
@@ -537,8 +723,8 @@ def bench_hbm(args):
                       "grid_point_updates_per_s": args.steps * res["iterations"] * npts / el,
                       "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                    "frac": round(gbs / PEAK_HBM_GBS, 4), "avg_launch_us": round(avg_s * 1e6, 1),
-                                   "launches": k["launches"],
-                                   "kernel": "stage_kernel_one<float, Quad6, Upwind1> (upwind + LF + Euler step)"}}),
+                                   "working_launches": nwork,
+                                   "kernel": "the FP32 upwind + LF + Euler stage kernel the tuner keeps"}}),
           flush=True)
 
 

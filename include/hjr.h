@@ -288,11 +288,15 @@ hjr_status hjr_stage_device(const hjr_grid *grid, const hjr_dynamics *dyn, int32
  * the stream are not counted) and accumulate the durations; hjr_profile_read returns the totals
  * since the last reset.  `launches` counts kernel launches (one per model/scheme group and
  * stage); `nodes` counts grid nodes covered by their tile lists (including nodes of instances
- * that had already finished). */
+ * that had already finished).  `working_launches` and `working_ms` count only the launches of
+ * steps that at least one instance of the launch's group was still taking (in the other launches
+ * every workgroup returns at once, after convergence); roofline figures use these. */
 typedef struct {
     int64_t launches;
     int64_t nodes;
     double ms;
+    int64_t working_launches;
+    double working_ms;
 } hjr_kernel_time;
 typedef struct {
     hjr_kernel_time stage32[3];   /* FP32 stage kernels, by RK stage (Euler uses [0]) */

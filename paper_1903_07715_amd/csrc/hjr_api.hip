@@ -518,9 +518,18 @@ static SolveState initial_state(const Request &r)
 // HJR_TUNE_CACHE=<file> the choices are also kept in a small JSON file for later processes.
 // --------------------------------------------------------------------------------------------
 
-static const int kNptCandidates[] = {4, 2, 8, 1};
-static const int kNptSchedule[] = {4, 2, 8, 1, 4};
-static const int kNptScheduleLen = (int)(sizeof kNptSchedule / sizeof kNptSchedule[0]);
+// Launch configurations: 1, 2, 4, 8 = flat tiles with that many nodes per thread; kMarchFull =
+// the plane-march kernel over whole dim-0 lines, kMarch8 = the same in runs of 8 planes (more
+// threads, two extra loads per run).  The march kernel serves first-order upwind groups whose
+// dim-0 planes hold enough columns to fill the device.
+static const int kMarchFull = -1;
+static const int kMarch8 = -8;
+static const int kFlatSchedule[] = {4, 2, 8, 1, 4};
+static const int kMarchSchedule[] = {4, kMarchFull, 2, 8, 1, kMarch8, 4};
+static const uint64_t kMarchMinColumns = 8192;
+
+static bool valid_config(int c) { return c == 1 || c == 2 || c == 4 || c == 8 || c == kMarchFull || c == kMarch8; }
+static bool is_march(int c) { return c < 0; }
 
 class Tuner {
 public:
@@ -529,13 +538,24 @@ public:
         static Tuner *t = new Tuner();
         return *t;
     }
-    static std::string key(int prec, int dyn, int spatial, uint64_t nodes)
+    // march: the group may use the plane-march kernel (its candidates are then timed too)
+    static std::string key(int prec, int dyn, int spatial, uint64_t nodes, bool march = false)
     {
         int b = 0;
         while ((2ull << b) <= nodes) ++b;
         char buf[64];
-        snprintf(buf, sizeof buf, "fp%d_dyn%d_sp%d_n2^%d", prec ? 64 : 32, dyn, spatial, b);
+        snprintf(buf, sizeof buf, "fp%d_dyn%d_sp%d_n2^%d%s", prec ? 64 : 32, dyn, spatial, b, march ? "_m" : "");
         return buf;
+    }
+    static bool march_key(const std::string &k) { return k.size() > 2 && k.compare(k.size() - 2, 2, "_m") == 0; }
+    static const int *schedule(const std::string &k, int *len)
+    {
+        if (march_key(k)) {
+            *len = (int)(sizeof kMarchSchedule / sizeof kMarchSchedule[0]);
+            return kMarchSchedule;
+        }
+        *len = (int)(sizeof kFlatSchedule / sizeof kFlatSchedule[0]);
+        return kFlatSchedule;
     }
     // The chosen nodes-per-thread, or 0 while candidates remain untimed.
     int choice(const std::string &k)
@@ -549,23 +569,29 @@ public:
     int next_candidate(const std::string &k)
     {
         std::lock_guard<std::mutex> g(mu_);
+        int len;
+        const int *sch = schedule(k, &len);
         const int n = count_[k];
-        return n < kNptScheduleLen ? kNptSchedule[n] : kNptCandidates[0];
+        return n < len ? sch[n] : sch[0];
     }
-    void record(const std::string &k, int npt, double us)
+    void record(const std::string &k, int config, double us)
     {
         std::lock_guard<std::mutex> g(mu_);
+        int len;
+        const int *sch = schedule(k, &len);
         auto &m = timed_[k];
-        m[npt] = m.count(npt) ? std::min(m[npt], us) : us;
-        if (++count_[k] < kNptScheduleLen) return;
-        for (int c : kNptCandidates)
-            if (!m.count(c)) return;
+        m[config] = m.count(config) ? std::min(m[config], us) : us;
+        if (++count_[k] < len) return;
+        for (int i = 0; i < len; ++i)
+            if (!m.count(sch[i])) return;
         // another candidate must beat the default by 8% (and the best so far by 2%): near-ties
         // keep the default, so the choice does not flip with timing noise from run to run
-        const int def = kNptCandidates[0];
+        const int def = sch[0];
         int best = def;
-        for (int c : kNptCandidates)
+        for (int i = 0; i < len; ++i) {
+            const int c = sch[i];
             if (m[c] < 0.92 * m[def] && m[c] < 0.98 * m[best]) best = c;
+        }
         chosen_[k] = best;
         save_file();
     }
@@ -596,7 +622,7 @@ private:
         while (fgets(line, sizeof line, f)) {
             char k[128];
             int v = 0;
-            if (sscanf(line, " \"%127[^\"]\" : %d", k, &v) == 2 && (v == 1 || v == 2 || v == 4 || v == 8))
+            if (sscanf(line, " \"%127[^\"]\" : %d", k, &v) == 2 && valid_config(v))
                 chosen_[k] = v;
         }
         fclose(f);
@@ -646,7 +672,7 @@ public:
         if (const char *mb = getenv("HJR_MAX_BLOCKS")) max_blocks_ = atoi(mb);
         if (const char *fu = getenv("HJR_FUSED")) fused_ = atoi(fu) != 0;
         if (const char *np = getenv("HJR_NPT")) npt_override_ = atoi(np);
-        if (npt_override_ != 1 && npt_override_ != 2 && npt_override_ != 4 && npt_override_ != 8) npt_override_ = 0;
+        if (!valid_config(npt_override_)) npt_override_ = 0;
         if (const char *at = getenv("HJR_AUTOTUNE")) autotune_ = atoi(at) != 0;
         if (const char *gr = getenv("HJR_GRAPHS")) graphs_ = atoi(gr) != 0;
         if (const char *pb = getenv("HJR_PLANE_BLOCK_BYTES")) plane_block_bytes_ = strtoull(pb, nullptr, 10);
@@ -668,9 +694,13 @@ public:
         Pool::get().release(d_insts_);
         Pool::get().release(d_tiles32_);
         Pool::get().release(d_tiles64_);
+        Pool::get().release(d_mtiles_[0]);
+        Pool::get().release(d_mtiles_[1]);
         d_states_ = nullptr;
         d_insts_ = nullptr;
         d_tiles32_ = d_tiles64_ = nullptr;
+        d_mtiles_[0] = d_mtiles_[1] = nullptr;
+        mtiles_cap_[0] = mtiles_cap_[1] = 0;
         if (h_states_) (void)hipHostFree(h_states_);
         if (h_insts_) (void)hipHostFree(h_insts_);
         if (h_tiles_) (void)hipHostFree(h_tiles_);
@@ -760,6 +790,7 @@ public:
     {
         const int ninst = top_slot_ + 1;
         for (int step = 0; step < m; ++step) {
+            cur_step_ = step;
             for (int stage = 0; stage < max_stages_; ++stage) {
                 for (int prec = 0; prec < 2; ++prec) {
                     hjr_status s = launch_stage_all(prec, stage, prof);
@@ -789,6 +820,10 @@ public:
         const int ninst = top_slot_ + 1;
         const bool prof = g_profile_on.load() != 0;
         nev_ = 0;
+        // where each instance stood before the chunk, to tell working launches from the ones
+        // issued after it finished (profile accounting)
+        before_.resize(ninst);
+        for (int i = 0; i < ninst; ++i) before_[i] = {h_states_[i].phase, h_states_[i].n, h_states_[i].done};
         bool done = false;
         bool exploring = false;
         for (int p = 0; p < 2; ++p)
@@ -846,6 +881,10 @@ public:
                 kt.launches += 1;
                 kt.nodes += e.nodes;
                 kt.ms += ms;
+                if (launch_worked(e)) {
+                    kt.working_launches += 1;
+                    kt.working_ms += ms;
+                }
             }
             // the median launch of the chunk (launches after an instance has finished return
             // at once and would drag a mean down)
@@ -853,7 +892,11 @@ public:
                 auto &v = kv.second;
                 std::sort(v.begin(), v.end());
                 const Seg &sg = segs_[kv.first.first][kv.first.second];
-                if (v.size() >= 3) {
+                // a chunk in which one of the group's instances finished (or changed phase) ran
+                // launches that return at once; its timing says nothing about the candidate
+                bool running = true;
+                for (int i : sg.slots) running = running && h_states_[i].done == kRunning;
+                if (running && v.size() >= 3) {
                     Tuner::get().record(sg.tune_key, sg.npt, 1e3 * v[v.size() / 2]);
                     if (getenv("HJR_TUNE_VERBOSE"))
                         fprintf(stderr, "[hjr tune] %s npt=%d launches=%zu min=%.1fus median=%.1fus max=%.1fus\n",
@@ -985,14 +1028,44 @@ private:
         int prec, stage;
         int64_t nodes;
         int group;  // >= 0: autotuner timing of segs_[prec][group]; -1: kernel profile
+        int seg;    // the launch's group in segs_[prec] (-1: the fused kernel)
+        int step;   // the step of the chunk the launch belongs to
     };
     struct Hist {
         int phase = -1;
         long long n = 0;
         double delta = 0.0;
     };
+    struct Before {
+        int phase;
+        long long n;
+        int done;
+    };
 
-    hjr_status event_pair(hipEvent_t *a, hipEvent_t *b, int prec, int stage, int64_t nodes, int group)
+    // Steps of the last chunk that instance i took (in the phase it ended the chunk in).
+    long long steps_taken(int i) const
+    {
+        const SolveState &a = h_states_[i];
+        const Before &b = before_[i];
+        if (b.done != kRunning && a.phase == b.phase) return 0;  // already finished, or idle slot
+        return a.phase != b.phase ? a.n : a.n - b.n;
+    }
+    // Whether some instance of the launch's group (every instance, for the fused kernel) was
+    // still taking the launch's step.
+    bool launch_worked(const EvRec &e) const
+    {
+        if (e.seg < 0) {
+            for (int i = 0; i <= top_slot_ && i < (int)before_.size(); ++i)
+                if (slots_[i] && steps_taken(i) > e.step) return true;
+            return false;
+        }
+        for (int i : segs_[e.prec][e.seg].slots)
+            if (i < (int)before_.size() && steps_taken(i) > e.step) return true;
+        return false;
+    }
+
+
+    hjr_status event_pair(hipEvent_t *a, hipEvent_t *b, int prec, int stage, int64_t nodes, int group, int seg = -1)
     {
         if (nev_ == (int)evs_.size()) {
             EvRec e{};
@@ -1005,6 +1078,8 @@ private:
         e.stage = stage;
         e.nodes = nodes;
         e.group = group;
+        e.seg = seg;
+        e.step = cur_step_;
         *a = e.a;
         *b = e.b;
         return HJR_OK;
@@ -1017,6 +1092,8 @@ private:
             std::vector<int> slots;
             uint64_t nodes = 0;
             uint64_t largest = 0;  // size class for the tuner: the group's largest instance
+            uint64_t min_cols = ~0ull;  // the fewest columns (nodes per dim-0 plane) of its grids
+            bool march_ok = true;
         };
         std::map<int, G> groups[2];
         top_slot_ = -1;
@@ -1033,34 +1110,45 @@ private:
             g.slots.push_back(i);
             g.nodes += r->npts;
             g.largest = std::max(g.largest, r->npts);
+            g.min_cols = std::min(g.min_cols, r->npts / (uint64_t)r->grid.n[0]);
+            g.march_ok = g.march_ok && r->opts.spatial == HJR_UPWIND1 && r->grid.ndim >= 2 && !r->inst.act;
         }
         if (top_slot_ < 0) top_slot_ = 0;
         std::vector<Tile> t[2];
+        std::vector<MTile> mt[2];
         for (int p = 0; p < 2; ++p) {
             segs_[p].clear();
             for (auto &kv : groups[p]) {
                 const bool local = kv.first >= kLocalKey;
                 const int dyn = (kv.first % kLocalKey) / 8, sp = kv.first % 8;
-                int npt = kFusedNpt;
+                // the march kernel addresses each field with 32-bit byte offsets
+                const bool march_ok = kv.second.march_ok && kv.second.min_cols >= kMarchMinColumns &&
+                                      kv.second.largest * (p ? 8ull : 4ull) <= 0xffffffffull;
+                int cfg = kFusedNpt;
                 std::string tkey;
                 if (local && !fused_) {
-                    npt = 4;  // the local-update kernels exist for 4 nodes per thread only
+                    cfg = 4;  // the local-update kernels exist for 4 nodes per thread only
                 } else if (!fused_) {
-                    npt = npt_override_;
-                    if (!npt) {
-                        const std::string k = Tuner::key(p, dyn, sp, kv.second.largest);
-                        npt = Tuner::get().choice(k);
-                        if (!npt && autotune_) {
-                            npt = Tuner::get().next_candidate(k);
+                    cfg = npt_override_;
+                    if (cfg && is_march(cfg) && !march_ok) cfg = 4;
+                    if (!cfg) {
+                        const std::string k = Tuner::key(p, dyn, sp, kv.second.largest, march_ok);
+                        cfg = Tuner::get().choice(k);
+                        if (!cfg && autotune_) {
+                            cfg = Tuner::get().next_candidate(k);
                             tkey = k;  // this group's launches are timed this chunk
                         }
-                        if (!npt) npt = kFusedNpt;
+                        if (!cfg) cfg = kFusedNpt;
                     }
                 }
+                // flat tiles of every group (the interval kernel walks them); march groups also
+                // get their march tiles
                 const int off = (int)t[p].size();
-                append_tiles(kv.second.slots, npt, t[p]);
-                segs_[p].push_back(
-                    Seg{dyn, sp, npt, off, (int)t[p].size() - off, (int64_t)kv.second.nodes, tkey, local});
+                append_tiles(kv.second.slots, is_march(cfg) ? 4 : cfg, t[p]);
+                const int moff = (int)mt[p].size();
+                if (is_march(cfg)) append_march_tiles(kv.second.slots, cfg == kMarchFull ? 0 : -cfg, mt[p]);
+                segs_[p].push_back(Seg{dyn, sp, cfg, off, (int)t[p].size() - off, moff, (int)mt[p].size() - moff,
+                                       (int64_t)kv.second.nodes, tkey, local, kv.second.slots});
             }
         }
         n32_ = (int)t[0].size();
@@ -1071,6 +1159,10 @@ private:
         }
         hjr_status s = upload_tiles(t[0], t[1]);
         if (s != HJR_OK) return s;
+        for (int p = 0; p < 2; ++p) {
+            s = upload_march_tiles(p, mt[p]);
+            if (s != HJR_OK) return s;
+        }
         drop_graphs();
         dirty_ = false;
         return HJR_OK;
@@ -1105,6 +1197,31 @@ private:
                 }
             }
         }
+    }
+
+    // March tiles of each instance, `len` dim-0 planes each (0: the whole line), in XCD order.
+    void append_march_tiles(const std::vector<int> &slots, int len, std::vector<MTile> &out)
+    {
+        for (int i : slots) {
+            const Request *r = slots_[i];
+            march_tiles(i, r->grid.ndim, r->grid.n, len, out);
+        }
+    }
+
+    hjr_status upload_march_tiles(int p, const std::vector<MTile> &m)
+    {
+        if (m.empty()) return HJR_OK;
+        const size_t need = m.size() * sizeof(MTile);
+        // earlier copies from the staging buffer, and kernels reading the old list, must be done
+        HJR_HIP(hipStreamSynchronize(stream_));
+        if (need > mtiles_cap_[p]) {
+            Pool::get().release(d_mtiles_[p]);
+            d_mtiles_[p] = nullptr;
+            mtiles_cap_[p] = std::max(need * 2, (size_t)4096);
+            HJR_HIP(Pool::get().alloc((void **)&d_mtiles_[p], mtiles_cap_[p]));
+        }
+        HJR_HIP(hipMemcpy(d_mtiles_[p], m.data(), need, hipMemcpyHostToDevice));
+        return HJR_OK;
     }
 
     hjr_status upload_tiles(const std::vector<Tile> &a, const std::vector<Tile> &b)
@@ -1158,21 +1275,29 @@ private:
             const bool explore = !g.tune_key.empty() && !prof;
             hipEvent_t ga = nullptr, gb = nullptr;
             if (prof || explore) {
-                hjr_status s = event_pair(&ga, &gb, prec, stage, prof ? g.nodes : 0, prof ? -1 : gi);
+                hjr_status s = event_pair(&ga, &gb, prec, stage, prof ? g.nodes : 0, prof ? -1 : gi, gi);
                 if (s != HJR_OK) return s;
             }
-            HJR_HIP(launch_stage_one(prec != 0, g.dyn, g.spatial, g.npt, d_insts_, tl + g.off, g.count, stage,
-                                     max_blocks_, stream_, ga, gb, g.local));
+            if (is_march(g.npt))
+                HJR_HIP(launch_march(prec != 0, g.dyn, d_insts_, d_mtiles_[prec] + g.moff, g.mcount, stage, stream_,
+                                     ga, gb));
+            else
+                HJR_HIP(launch_stage_one(prec != 0, g.dyn, g.spatial, g.npt, d_insts_, tl + g.off, g.count, stage,
+                                         max_blocks_, stream_, ga, gb, g.local));
             ++launches_;
         }
         return HJR_OK;
     }
 
     struct Seg {
-        int dyn, spatial, npt, off, count;
+        int dyn, spatial;
+        int npt;               // launch configuration: nodes per thread, or kMarchFull / kMarch8
+        int off, count;        // flat tiles
+        int moff, mcount;      // march tiles
         int64_t nodes;         // nodes of the group's instances
         std::string tune_key;  // non-empty: this group is being timed for the autotuner
         bool local;            // instances with local updates (their own kernel variant)
+        std::vector<int> slots;  // the group's instances
     };
     static constexpr int kLocalKey = 1024;  // group key offset of local-update instances
     std::vector<Seg> segs_[2];
@@ -1193,6 +1318,8 @@ private:
     Tile *d_tiles32_ = nullptr, *d_tiles64_ = nullptr;
     Tile *h_tiles_ = nullptr;
     size_t tiles_cap_ = 0;
+    MTile *d_mtiles_[2] = {nullptr, nullptr};
+    size_t mtiles_cap_[2] = {0, 0};
     int n32_ = 0, n64_ = 0;
     int top_slot_ = 0, max_stages_ = 1;
     bool any_interval_ = false;
@@ -1203,6 +1330,8 @@ private:
     std::vector<Hist> hist_;
     std::vector<EvRec> evs_;
     int nev_ = 0;
+    std::vector<Before> before_;
+    int cur_step_ = 0;
     int nactive_ = 0;
     int64_t launches_ = 0, chunks_ = 0;
 };
@@ -1735,20 +1864,33 @@ hjr_status hjr_stage_device(const hjr_grid *grid, const hjr_dynamics *dyn, int32
     if (const char *fu = getenv("HJR_FUSED")) fused = atoi(fu) != 0;
     int npt = 0;
     if (const char *np = getenv("HJR_NPT")) npt = atoi(np);
-    if (npt != 1 && npt != 2 && npt != 4 && npt != 8) npt = 0;
-    if (!npt) npt = Tuner::get().choice(Tuner::key(f32 ? 0 : 1, dyn->id, spatial, r.npts));
+    if (!valid_config(npt)) npt = 0;
+    const uint64_t cols = r.npts / (uint64_t)grid->n[0];
+    const bool march_ok = spatial == HJR_UPWIND1 && grid->ndim >= 2 && cols >= kMarchMinColumns &&
+                          r.npts * (f32 ? 4ull : 8ull) <= 0xffffffffull;
+    if (is_march(npt) && !march_ok) npt = 0;
+    if (!npt) npt = Tuner::get().choice(Tuner::key(f32 ? 0 : 1, dyn->id, spatial, r.npts, march_ok));
     if (!npt || fused) npt = kFusedNpt;
     std::vector<Tile> tiles;
-    for (uint64_t s0 = 0; s0 < r.npts; s0 += (uint64_t)npt * kBlock) tiles.push_back(Tile{0, (uint32_t)s0, npt});
+    std::vector<MTile> mtiles;
+    if (is_march(npt)) {
+        march_tiles(0, grid->ndim, grid->n, npt == kMarchFull ? 0 : -npt, mtiles);
+    } else {
+        for (uint64_t s0 = 0; s0 < r.npts; s0 += (uint64_t)npt * kBlock) tiles.push_back(Tile{0, (uint32_t)s0, npt});
+    }
+    const size_t tl_bytes = is_march(npt) ? mtiles.size() * sizeof(MTile) : tiles.size() * sizeof(Tile);
+    const void *tl_host = is_march(npt) ? (const void *)mtiles.data() : (const void *)tiles.data();
     void *dtl = nullptr;
-    if (e == hipSuccess) e = Pool::get().alloc(&dtl, tiles.size() * sizeof(Tile));
+    if (e == hipSuccess) e = Pool::get().alloc(&dtl, tl_bytes);
     if (e == hipSuccess) e = hipMemcpyAsync((void *)I.tab64, t64.data(), t64.size() * 8, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync((void *)I.tab32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(dstate, &hs, sizeof hs, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(dinst, &I, sizeof I, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(dtl, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dtl, tl_host, tl_bytes, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
-        if (fused)
+        if (is_march(npt))
+            e = launch_march(!f32, dyn->id, dinst, (const MTile *)dtl, (int)mtiles.size(), k, st);
+        else if (fused)
             e = launch_stage(!f32, dinst, (const Tile *)dtl, (int)tiles.size(), k, 0, st);
         else
             e = launch_stage_one(!f32, dyn->id, spatial, npt, dinst, (const Tile *)dtl, (int)tiles.size(), k, 0, st);

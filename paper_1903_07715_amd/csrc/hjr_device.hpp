@@ -133,6 +133,17 @@ struct Tile {
     int npt;
 };
 
+// A march tile: cn <= kBlock consecutive columns (flat positions within a dim-0 plane, starting
+// at c0) of one instance, each advanced through the dim-0 planes i0 .. i0 + len - 1 by one
+// thread (cn = 0: a padding tile that does nothing).
+struct MTile {
+    int inst;
+    uint32_t c0;
+    int i0;
+    int len;
+    uint32_t cn;
+};
+
 template <typename T> struct Fields;
 template <> struct Fields<float> {
     __device__ static float *V(const Inst &I) { return I.V32; }
@@ -362,29 +373,60 @@ __device__ __forceinline__ void line_derivs(const T *u, int j, int n, bool perio
 // sgn = +1 for the avoid game, -1 for reach: control terms enter as +sgn*|.|, disturbance
 // terms as -sgn*|.|.
 // ---------------------------------------------------------------------------------------------
+// The per-node values a model's flow takes from the node's coordinates (read from the tables):
+// heading cosine and sine, speed or velocity coordinates.  No model's flow depends on the dim-0
+// coordinate, so along a dim-0 line these are fixed.
+template <typename T> struct HamCoef {
+    T a, b, c, d;
+};
+
 template <typename T, int DYN>
-__device__ __forceinline__ T hamiltonian(const Inst &I, const T *__restrict__ tab, const int *idx,
-                                         const T *p, T *alpha, T sgn)
+__device__ __forceinline__ HamCoef<T> ham_coef(const Inst &I, const T *__restrict__ tab, const int *idx)
+{
+    HamCoef<T> k{};
+    if constexpr (DYN == kDynDI) {
+        k.a = ldg(tab, I.coord_off[1] + idx[1]);                  // x2
+    } else if constexpr (DYN == kDynDubins) {
+        k.a = ldg(tab, I.trig_off + idx[2]);                      // cos theta
+        k.b = ldg(tab, I.trig_off + I.n[2] + idx[2]);             // sin theta
+    } else if constexpr (DYN == kDynUnicycle) {
+        k.a = ldg(tab, I.trig_off + idx[2]);
+        k.b = ldg(tab, I.trig_off + I.n[2] + idx[2]);
+        k.c = ldg(tab, I.coord_off[3] + idx[3]);                  // speed
+    } else if constexpr (DYN == kDynQ10XY) {
+        k.a = ldg(tab, I.coord_off[1] + idx[1]);                  // v
+        k.b = ldg(tab, I.coord_off[2] + idx[2]);                  // theta
+        k.c = ldg(tab, I.trig_off + idx[2]);                      // tan theta
+        k.d = ldg(tab, I.coord_off[3] + idx[3]);                  // omega
+    } else if constexpr (DYN == kDynQ10Z) {
+        k.a = ldg(tab, I.coord_off[1] + idx[1]);                  // v_z
+    } else {
+        k.a = ldg(tab, I.coord_off[3] + idx[3]);                  // v_x, v_y, v_z
+        k.b = ldg(tab, I.coord_off[4] + idx[4]);
+        k.c = ldg(tab, I.coord_off[5] + idx[5]);
+    }
+    return k;
+}
+
+template <typename T, int DYN>
+__device__ __forceinline__ T ham_eval(const Inst &I, const HamCoef<T> &k, const T *p, T *alpha, T sgn)
 {
     using F = Fields<T>;
     if constexpr (DYN == kDynDI) {
-        T x2 = ldg(tab, I.coord_off[1] + idx[1]);
+        T x2 = k.a;
         T cu = F::c(I, 0), dd = F::c(I, 1);
         alpha[0] = fabs(x2) + dd;
         alpha[1] = cu;
         return p[0] * x2 + sgn * (cu * fabs(p[1]) - dd * fabs(p[0]));
     } else if constexpr (DYN == kDynDubins) {
-        T cs = ldg(tab, I.trig_off + idx[2]);
-        T sn = ldg(tab, I.trig_off + I.n[2] + idx[2]);
+        T cs = k.a, sn = k.b;
         T v = F::c(I, 0), ub = F::c(I, 1), d1 = F::c(I, 2), d2 = F::c(I, 3);
         alpha[0] = fabs(v * cs) + d1;
         alpha[1] = fabs(v * sn) + d2;
         alpha[2] = ub;
         return v * (p[0] * cs + p[1] * sn) + sgn * (ub * fabs(p[2]) - d1 * fabs(p[0]) - d2 * fabs(p[1]));
     } else if constexpr (DYN == kDynUnicycle) {
-        T cs = ldg(tab, I.trig_off + idx[2]);
-        T sn = ldg(tab, I.trig_off + I.n[2] + idx[2]);
-        T v = ldg(tab, I.coord_off[3] + idx[3]);
+        T cs = k.a, sn = k.b, v = k.c;
         T u1 = F::c(I, 0), u2 = F::c(I, 1), dd = F::c(I, 2);
         alpha[0] = fabs(v * cs) + dd;
         alpha[1] = fabs(v * sn) + dd;
@@ -394,10 +436,7 @@ __device__ __forceinline__ T hamiltonian(const Inst &I, const T *__restrict__ ta
         return v * (p[0] * cs + p[1] * sn) + sgn * (u1 * fabs(p[2]) + u2 * fabs(p[3]) - dist);
     } else if constexpr (DYN == kDynQ10XY) {
         // c0 = g, c1 = d0, c2 = d1, c3 = n0 S_max, c4 = dbar; the table holds tan(theta)
-        T v = ldg(tab, I.coord_off[1] + idx[1]);
-        T th = ldg(tab, I.coord_off[2] + idx[2]);
-        T tn = ldg(tab, I.trig_off + idx[2]);
-        T om = ldg(tab, I.coord_off[3] + idx[3]);
+        T v = k.a, th = k.b, tn = k.c, om = k.d;
         T f1 = F::c(I, 0) * tn, f2 = om - F::c(I, 2) * th, f3 = -F::c(I, 1) * th;
         T ns = F::c(I, 3), dd = F::c(I, 4);
         alpha[0] = fabs(v) + dd;
@@ -407,16 +446,14 @@ __device__ __forceinline__ T hamiltonian(const Inst &I, const T *__restrict__ ta
         return p[0] * v + p[1] * f1 + p[2] * f2 + p[3] * f3 + sgn * (ns * fabs(p[3]) - dd * fabs(p[0]));
     } else if constexpr (DYN == kDynQ10Z) {
         // c0 = (k_T/m) T_max - g, c1 = (k_T/m) T_min - g, c2 = dbar, c3 = max(|c0|, |c1|)
-        T vz = ldg(tab, I.coord_off[1] + idx[1]);
+        T vz = k.a;
         alpha[0] = fabs(vz) + F::c(I, 2);
         alpha[1] = F::c(I, 3);
         // the thrust picks T_max or T_min by the sign of p_vz (avoid: maximise)
         T thrust = (sgn * p[1] > T(0)) ? p[1] * F::c(I, 0) : p[1] * F::c(I, 1);
         return p[0] * vz + thrust - sgn * F::c(I, 2) * fabs(p[0]);
     } else {
-        T vx = ldg(tab, I.coord_off[3] + idx[3]);
-        T vy = ldg(tab, I.coord_off[4] + idx[4]);
-        T vz = ldg(tab, I.coord_off[5] + idx[5]);
+        T vx = k.a, vy = k.b, vz = k.c;
         T ax = F::c(I, 0), ay = F::c(I, 1), tmax = F::c(I, 2), tmin = F::c(I, 3);
         T dx = F::c(I, 4), dy = F::c(I, 5), dz = F::c(I, 6);
         alpha[0] = fabs(vx);
@@ -431,6 +468,13 @@ __device__ __forceinline__ T hamiltonian(const Inst &I, const T *__restrict__ ta
         return p[0] * vx + p[1] * vy + p[2] * vz + thrust +
                sgn * (ax * fabs(p[3]) + ay * fabs(p[4]) - dx * fabs(p[3]) - dy * fabs(p[4]) - dz * fabs(pz));
     }
+}
+
+template <typename T, int DYN>
+__device__ __forceinline__ T hamiltonian(const Inst &I, const T *__restrict__ tab, const int *idx,
+                                         const T *p, T *alpha, T sgn)
+{
+    return ham_eval<T, DYN>(I, ham_coef<T, DYN>(I, tab, idx), p, alpha, sgn);
 }
 
 template <int DYN> struct DynDim;

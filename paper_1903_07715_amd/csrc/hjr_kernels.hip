@@ -9,6 +9,9 @@
 // loop over its XCD's run (persistent mode).
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "hjr_kernels.hpp"
 
 namespace hjr {
@@ -271,6 +274,219 @@ __global__ __launch_bounds__(kBlock) void stage_kernel_one(const Inst *__restric
         if (LOCAL && !tile_active(I, st, tl.start, (uint32_t)(NPT * kBlock))) continue;
         stage_tile<T, DYN, SPATIAL, NPT, LOCAL>(I, tl.start, stage, (T)st->dt_cur, red);
     }
+}
+
+// --------------------------------------------------------------------------------------------
+// Plane-march stage kernel (first-order upwind stencils)
+//
+// Each thread owns one column of the grid (a position within a dim-0 plane) and advances it
+// through a run of consecutive dim-0 planes.  The column's indices in dims 1.., its stencil
+// offsets, its edge rule and the model's coordinate values are worked out once, not per node,
+// and the dim-0 neighbours are carried from one plane to the next in registers, so per node
+// the thread loads the next plane's value, the 2 (ndim - 1) neighbours within the plane and
+// l, and writes one value.  Consecutive lanes hold consecutive columns, so every load and
+// store of a wave is one contiguous run.  The per-node arithmetic is that of stage_tile
+// (bitwise the same results).
+// --------------------------------------------------------------------------------------------
+
+// Buffer accesses: a resource descriptor (a field's base address and size, in scalar registers)
+// plus a per-lane 32-bit byte offset and a uniform 32-bit byte offset.  A column's offsets stay
+// fixed from plane to plane and only the uniform plane offset moves, so a load or store needs no
+// per-lane address arithmetic and one scalar add per plane.  The host only hands the kernel
+// fields below 4 GiB; offsets at or beyond the field's size would read zero and drop writes
+// instead of faulting.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const void *base, size_t bytes)
+{
+    const uint32_t n = bytes > 0xffffffffull ? 0xffffffffu : (uint32_t)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)n, 0x00020000);
+}
+template <typename T> __device__ __forceinline__ T bld(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff);
+template <> __device__ __forceinline__ float bld<float>(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+}
+template <> __device__ __forceinline__ double bld<double>(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
+}
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, soff, 0);
+}
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff, double v)
+{
+    using u2 = unsigned int __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, soff, 0);
+}
+
+template <typename T, int DYN>
+__device__ __forceinline__ void march_tile(const Inst &I, const MTile &tl, int stage, T dt, double *red)
+{
+    constexpr int N = DynDim<DYN>::value;
+    using F = Fields<T>;
+    SolveState *st = I.state;
+    const bool euler = I.temporal == kEuler;
+    const int par = euler ? st->parity : 0;
+    T *V = F::V(I), *A = F::A(I), *B = F::B(I);
+    const T *S, *Vn;
+    T *O;
+    if (euler) {
+        S = par ? A : V;
+        Vn = S;
+        O = par ? V : A;
+    } else if (stage == 0) {
+        S = V; Vn = V; O = A;
+    } else if (stage == 1) {
+        S = A; Vn = V; O = B;
+    } else {
+        S = B; Vn = V; O = V;
+    }
+    const bool last = euler || stage == 2;
+    const T *G = uniform_ptr(F::g(I));  // reach-avoid constraint, or nullptr
+    const size_t fbytes = (size_t)I.npts * sizeof(T);
+    const __amdgpu_buffer_rsrc_t rS = buf(uniform_ptr(S), fbytes), rVn = buf(uniform_ptr(Vn), fbytes);
+    const __amdgpu_buffer_rsrc_t rO = buf(uniform_ptr(O), fbytes), rl = buf(uniform_ptr(F::l(I)), fbytes);
+    const __amdgpu_buffer_rsrc_t rG = buf(G, fbytes);
+    const T gm = (T)st->gamma;
+    const uint32_t P = I.stride[0];                       // columns (nodes per dim-0 plane)
+    const uint32_t pb = P * (uint32_t)sizeof(T);          // bytes per plane
+    const int n0 = I.n[0];
+    const bool per0 = I.periodic & 1u;
+    const uint32_t c = tl.c0 + threadIdx.x;
+    T delta = T(0);
+    if (threadIdx.x < tl.cn) {
+        int idx[N];
+        idx[0] = 0;
+        uint32_t rem = c;
+#pragma unroll
+        for (int d = N - 1; d >= 2; --d) {
+            const uint32_t q = fdiv(rem, I.div[d]);
+            idx[d] = (int)(rem - q * (uint32_t)I.n[d]);
+            rem = q;
+        }
+        if (N >= 2) idx[1] = (int)rem;
+        // Byte offsets of the -/+ neighbours within the plane and the sign that applies the
+        // edge rule: at a non-periodic end the missing neighbour is replaced by the one on the
+        // other side and the difference negated, which gives the interior difference exactly
+        // (the rule of line_derivs); periodic dims wrap.
+        uint32_t om[N], op[N];
+        T sm[N], sp[N];
+#pragma unroll
+        for (int d = 1; d < N; ++d) {
+            const int j = idx[d], n = I.n[d];
+            const int s = d == N - 1 ? 1 : (int)I.stride[d];
+            int m, q;
+            T a, b;
+            if ((I.periodic >> d) & 1u) {
+                m = j > 0 ? -1 : n - 1;
+                q = j < n - 1 ? 1 : 1 - n;
+                a = b = T(1);
+            } else {
+                m = j > 0 ? -1 : 1;
+                q = j < n - 1 ? 1 : -1;
+                a = j > 0 ? T(1) : T(-1);
+                b = j < n - 1 ? T(1) : T(-1);
+            }
+            om[d] = (uint32_t)((int)c + m * s) * (uint32_t)sizeof(T);
+            op[d] = (uint32_t)((int)c + q * s) * (uint32_t)sizeof(T);
+            sm[d] = a;
+            sp[d] = b;
+        }
+        const HamCoef<T> kc = ham_coef<T, DYN>(I, uniform_ptr(F::tab(I)), idx);
+        const T sgn = I.game == 0 ? T(1) : T(-1);
+        const uint32_t cb = c * (uint32_t)sizeof(T);
+        const int i0 = tl.i0, i1 = tl.i0 + tl.len;
+        const bool proj = last && !I.brs;
+        const bool useg = last && G != nullptr;
+        // values of S at planes i - 1 and i; at a non-periodic end the centre stands in for the
+        // missing neighbour (its difference is replaced below)
+        const int im = i0 > 0 ? i0 - 1 : (per0 ? n0 - 1 : 0);
+        T um = bld<T>(rS, cb, (uint32_t)im * pb);
+        T u0 = bld<T>(rS, cb, (uint32_t)i0 * pb);
+        uint32_t so = (uint32_t)i0 * pb;  // byte offset of plane i
+        for (int i = i0; i < i1; ++i, so += pb) {
+            // every load of the node first (the next plane's value, the neighbours within the
+            // plane, l, the constraint, the step-start value), so they are in flight together
+            struct {
+                T up, un[N], unp[N], lv, gv, vn;
+            } cur;
+            {
+                const uint32_t sp1 = i + 1 < n0 ? so + pb : (per0 ? 0u : so);
+                cur.up = bld<T>(rS, cb, sp1);
+#pragma unroll
+                for (int d = 1; d < N; ++d) {
+                    cur.un[d] = bld<T>(rS, om[d], so);
+                    cur.unp[d] = bld<T>(rS, op[d], so);
+                }
+                cur.lv = proj ? bld<T>(rl, cb, so) : T(0);
+                cur.gv = useg ? bld<T>(rG, cb, so) : T(0);
+                cur.vn = euler ? T(0) : bld<T>(rVn, cb, so);
+            }
+            const T up = cur.up;
+            T p[N], diff[N], alpha[N];
+            {
+                T dm = u0 - um, dq = up - u0;
+                if (!per0) {
+                    const T r0 = dm, r1 = dq;
+                    dm = i == 0 ? r1 : r0;
+                    dq = i == n0 - 1 ? r0 : r1;
+                }
+                const T h = F::hinv_dx(I, 0);
+                p[0] = h * (dm + dq);
+                diff[0] = h * (dq - dm);
+            }
+#pragma unroll
+            for (int d = 1; d < N; ++d) {
+                const T dm = sm[d] * (u0 - cur.un[d]);
+                const T dq = sp[d] * (cur.unp[d] - u0);
+                const T h = F::hinv_dx(I, d);
+                p[d] = h * (dm + dq);
+                diff[d] = h * (dq - dm);
+            }
+            T L = ham_eval<T, DYN>(I, kc, p, alpha, sgn);
+#pragma unroll
+            for (int d = 0; d < N; ++d) L += alpha[d] * diff[d];
+            const T s = u0;
+            const T vn = euler ? u0 : cur.vn;
+            T out;
+            if (euler) {
+                out = gm * (s + dt * L);
+                if (!I.brs) out = fmin(cur.lv, out);
+                if (G) out = fmax(cur.gv, out);
+            } else if (stage == 0) {
+                out = s + dt * L;
+            } else if (stage == 1) {
+                out = T(0.75) * vn + T(0.25) * (s + dt * L);
+            } else {
+                out = gm * (vn * T(1.0 / 3.0) + T(2.0 / 3.0) * (s + dt * L));
+                if (!I.brs) out = fmin(cur.lv, out);
+                if (G) out = fmax(cur.gv, out);
+            }
+            bst(rO, cb, so, out);
+            if (last) delta = nanmax(delta, T(fabs(out - vn)));
+            um = u0;
+            u0 = up;
+        }
+    }
+    if (last) block_max_to((double)delta, &st->delta_bits, red);
+}
+
+// One workgroup per tile, in list order: workgroups are dealt to the 8 XCDs round-robin
+// (workgroup b to XCD b mod 8), and the host interleaves the list so that each XCD receives
+// compact blocks of neighbouring tiles.
+template <typename T, int DYN>
+__global__ __launch_bounds__(kBlock) void march_kernel(const Inst *__restrict__ insts, const MTile *__restrict__ tiles,
+                                                       int ntiles, int stage)
+{
+    __shared__ double red[kBlock / 64];
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const MTile tl = tiles[t];
+    if (tl.cn == 0) return;  // padding
+    const Inst &I = insts[tl.inst];
+    const SolveState *st = I.state;
+    if (st->done != kRunning || stage >= I.nstages) return;
+    march_tile<T, DYN>(I, tl, stage, (T)st->dt_cur, red);
 }
 
 // --------------------------------------------------------------------------------------------
@@ -644,6 +860,104 @@ hipError_t launch_stage_one(bool fp64, int dyn, int spatial, int npt, const Inst
         launch_one<double>(dyn, spatial, npt, local, g, s, insts, tiles, ntiles, stage, ev0, ev1);
     else
         launch_one<float>(dyn, spatial, npt, local, g, s, insts, tiles, ntiles, stage, ev0, ev1);
+    return hipGetLastError();
+}
+
+template <typename T>
+static void launch_march_t(int dyn, dim3 g, hipStream_t s, const Inst *insts, const MTile *tiles, int ntiles,
+                           int stage, hipEvent_t ev0, hipEvent_t ev1)
+{
+#define HJR_MARCH(D)                                                                                           \
+    do {                                                                                                       \
+        if (ev0 || ev1)                                                                                        \
+            hipExtLaunchKernelGGL((march_kernel<T, D>), g, dim3(kBlock), 0, s, ev0, ev1, 0u, insts, tiles, ntiles, \
+                                  stage);                                                                      \
+        else                                                                                                   \
+            hipLaunchKernelGGL((march_kernel<T, D>), g, dim3(kBlock), 0, s, insts, tiles, ntiles, stage);      \
+    } while (0)
+    switch (dyn) {
+    case kDynDI: HJR_MARCH(kDynDI); break;
+    case kDynDubins: HJR_MARCH(kDynDubins); break;
+    case kDynUnicycle: HJR_MARCH(kDynUnicycle); break;
+    case kDynQuad: HJR_MARCH(kDynQuad); break;
+    case kDynQ10XY: HJR_MARCH(kDynQ10XY); break;
+    case kDynQ10Z: HJR_MARCH(kDynQ10Z); break;
+    default: break;
+    }
+#undef HJR_MARCH
+}
+
+void march_tiles(int inst, int ndim, const int *n, int len, std::vector<MTile> &out)
+{
+    const int n0 = n[0];
+    const int L = len > 0 ? std::min(len, n0) : n0;
+    uint64_t P = 1;
+    for (int d = 1; d < ndim; ++d) P *= (uint64_t)n[d];
+    // rows of consecutive columns: over dims 1 and 2 when the dims after them hold at least
+    // 4 kBlock columns, else over dim 1 when the dims after it do, else one row
+    const uint64_t minrow = 4 * (uint64_t)kBlock;
+    uint64_t na = 1, nb = 1;
+    if (ndim >= 4 && P / ((uint64_t)n[1] * n[2]) >= minrow) {
+        na = (uint64_t)n[1];
+        nb = (uint64_t)n[2];
+    } else if (ndim >= 3 && P / (uint64_t)n[1] >= minrow) {
+        na = (uint64_t)n[1];
+    }
+    const uint64_t R = P / (na * nb);                     // columns per row
+    const uint64_t tr = (R + kBlock - 1) / kBlock;        // tiles per row
+    // blocks of about 256 column tiles: Bt neighbouring tiles of Ba x Bb neighbouring rows
+    const uint64_t Bt = std::min<uint64_t>(tr, 16);
+    uint64_t Ba = 1, Bb = 1;
+    const uint64_t rest = std::max<uint64_t>(1, 256 / Bt);
+    if (nb > 1) {
+        while ((Ba + 1) * (Ba + 1) <= rest) ++Ba;
+        Bb = Ba;
+    } else {
+        Ba = rest;
+    }
+    Ba = std::min(Ba, na);
+    Bb = std::min(Bb, nb);
+    std::vector<std::vector<MTile>> blocks;
+    for (uint64_t a0 = 0; a0 < na; a0 += Ba)
+        for (uint64_t b0 = 0; b0 < nb; b0 += Bb)
+            for (uint64_t t0 = 0; t0 < tr; t0 += Bt) {
+                std::vector<MTile> blk;
+                for (uint64_t a = a0; a < std::min(na, a0 + Ba); ++a)
+                    for (uint64_t b = b0; b < std::min(nb, b0 + Bb); ++b)
+                        for (uint64_t t = t0; t < std::min(tr, t0 + Bt); ++t) {
+                            const uint64_t c0 = (a * nb + b) * R + t * kBlock;
+                            const uint32_t cn = (uint32_t)std::min<uint64_t>(kBlock, R - t * kBlock);
+                            for (int i0 = 0; i0 < n0; i0 += L)
+                                blk.push_back(MTile{inst, (uint32_t)c0, i0, std::min(L, n0 - i0), cn});
+                        }
+                blocks.push_back(std::move(blk));
+            }
+    // rounds of 8 blocks, one per XCD, interleaved workgroup by workgroup; the blocks are taken
+    // largest first (the blocks at the high ends of the index ranges are smaller) so that the
+    // blocks of a round are of about the same size and little padding is needed; a last round of
+    // fewer blocks is appended in plain order
+    std::stable_sort(blocks.begin(), blocks.end(),
+                     [](const std::vector<MTile> &a, const std::vector<MTile> &b) { return a.size() > b.size(); });
+    const size_t nb8 = blocks.size() / 8 * 8;
+    for (size_t r = 0; r < nb8; r += 8) {
+        size_t m = 0;
+        for (size_t x = 0; x < 8; ++x) m = std::max(m, blocks[r + x].size());
+        for (size_t k = 0; k < m; ++k)
+            for (size_t x = 0; x < 8; ++x)
+                out.push_back(k < blocks[r + x].size() ? blocks[r + x][k] : MTile{inst, 0u, 0, 0, 0u});
+    }
+    for (size_t r = nb8; r < blocks.size(); ++r) out.insert(out.end(), blocks[r].begin(), blocks[r].end());
+}
+
+hipError_t launch_march(bool fp64, int dyn, const Inst *insts, const MTile *tiles, int ntiles, int stage,
+                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const dim3 g(ntiles);
+    if (fp64)
+        launch_march_t<double>(dyn, g, s, insts, tiles, ntiles, stage, ev0, ev1);
+    else
+        launch_march_t<float>(dyn, g, s, insts, tiles, ntiles, stage, ev0, ev1);
     return hipGetLastError();
 }
 

@@ -1,6 +1,8 @@
 // hjr_kernels.hpp -- launch wrappers of the HJI VI kernels (host side).
 #pragma once
 
+#include <vector>
+
 #include "hjr_device.hpp"
 
 namespace hjr {
@@ -11,6 +13,19 @@ hipError_t launch_stage(bool fp64, const Inst *insts, const Tile *tiles, int nti
 hipError_t launch_stage_one(bool fp64, int dyn, int spatial, int npt, const Inst *insts, const Tile *tiles, int ntiles,
                             int stage, int max_blocks, hipStream_t s, hipEvent_t ev0 = nullptr,
                             hipEvent_t ev1 = nullptr, bool local = false);
+// First-order upwind stages by the plane-march kernel: one thread per column, advancing through
+// the dim-0 planes of its tile; one workgroup per tile in list order (see march_tiles for the
+// order).  Every field of the instances must be below 4 GiB.
+hipError_t launch_march(bool fp64, int dyn, const Inst *insts, const MTile *tiles, int ntiles, int stage,
+                        hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
+// The march tiles of one instance (grid dims n[0..ndim), its index `inst`), in the order its
+// workgroups should run: columns are cut into tiles of at most kBlock consecutive columns within
+// a row of the innermost dims, tiles are grouped into blocks of neighbouring rows (several
+// dim-1 and dim-2 indices) and neighbouring tiles, and the blocks are interleaved so that
+// workgroup b, which runs on XCD b mod 8, belongs to block 8 s + (b mod 8) of round s; padding
+// tiles (cn = 0) keep that correspondence.  len: planes per tile (0: the whole dim-0 line).
+void march_tiles(int inst, int ndim, const int *n, int len, std::vector<MTile> &out);
 hipError_t launch_step_end(const Inst *insts, int ninst, hipStream_t s);
 hipError_t launch_interval(bool fp64, const Inst *insts, const Tile *tiles, int ntiles, int max_blocks,
                            hipStream_t s);

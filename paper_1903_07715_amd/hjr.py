@@ -72,7 +72,8 @@ class CtxStats_(C.Structure):
 
 
 class KernelTime_(C.Structure):
-    _fields_ = [("launches", C.c_int64), ("nodes", C.c_int64), ("ms", C.c_double)]
+    _fields_ = [("launches", C.c_int64), ("nodes", C.c_int64), ("ms", C.c_double), ("working_launches", C.c_int64),
+                ("working_ms", C.c_double)]
 
 
 class Profile_(C.Structure):
@@ -386,13 +387,16 @@ def profile_enable(on: bool = True) -> None:
 
 
 def profile_read(reset: bool = False) -> dict:
-    """Stage-kernel launch counts, covered nodes and event-timed milliseconds since the last reset."""
+    """Stage-kernel launch counts, covered nodes and event-timed milliseconds since the last reset,
+    in total and over working launches only (steps some instance of the group was still taking)."""
     p = Profile_()
     _check(load().hjr_profile_read(C.byref(p), 1 if reset else 0))
     out = {}
     for prec in ("stage32", "stage64"):
         arr = getattr(p, prec)
-        out[prec] = [dict(launches=arr[i].launches, nodes=arr[i].nodes, ms=arr[i].ms) for i in range(3)]
+        out[prec] = [dict(launches=arr[i].launches, nodes=arr[i].nodes, ms=arr[i].ms,
+                          working_launches=arr[i].working_launches, working_ms=arr[i].working_ms)
+                     for i in range(3)]
     return out
 
 

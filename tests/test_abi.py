@@ -46,7 +46,8 @@ def test_struct_layouts_match_header():
     subprocess.run(["gcc", "-std=c11", "-o", exe, os.path.join(ROOT, "tests", "native", "abi_layout.c")], check=True)
     got = dict(ln.split() for ln in subprocess.run([exe], capture_output=True, text=True).stdout.splitlines())
     mirrors = {"hjr_grid": hjr.Grid_, "hjr_dynamics": hjr.Dynamics_, "hjr_options": hjr.Options_,
-               "hjr_result": hjr.Result_, "hjr_problem": hjr.Problem_, "hjr_ctx_stats": hjr.CtxStats_}
+               "hjr_result": hjr.Result_, "hjr_problem": hjr.Problem_, "hjr_ctx_stats": hjr.CtxStats_,
+               "hjr_kernel_time": hjr.KernelTime_, "hjr_profile": hjr.Profile_}
     for name, cls in mirrors.items():
         assert int(got[name]) == C.sizeof(cls), name
     for key, val in got.items():
