@@ -1,0 +1,119 @@
+"""Converged FP32 + FP64-polish solves at the benchmark configurations against the FP64 oracle.
+
+For each result the test prints and bounds max |V - V_oracle| and the number of nodes where the
+two disagree on the sign of V while |V_oracle| > 1e-4 max|l| (the unsafe set {V <= 0} off the
+tolerance band).  Bars: max |V - V_oracle| <= 1e-4 max|l| and no such node.  Warm starts take
+the oracle's own prior solution as k on both sides, so no oracle input comes from the GPU.
+
+  * 3-D Dubins car 101^3, WENO5 + TVD-RK3: cold, and warm-started from the solution with the
+    disturbance bound halved (exact by Theorem 2).  The FP64 polish starts from
+    min(l, V32 + 2 tol32); the test also counts the nodes where that start lies below the
+    oracle's solution (the polish is exact when it starts above it).
+  * 6-D quadrotor (the benchmark's problem) on 9^6, upwind + Euler: cold, and warm-started from
+    the solution with disturbance 0.3 (the new problem has 0.5).
+"""
+import numpy as np
+import pytest
+
+from paper_1903_07715_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _figures(name, V, Vo, l):
+    band = 1e-4 * float(np.abs(l).max())
+    err = float(np.abs(V - Vo).max())
+    mism = int(np.sum(((V <= 0) != (Vo <= 0)) & (np.abs(Vo) > band)))
+    print(f"[converged] {name}: max|V - V_oracle| = {err:.3e} (bar {band:.3e}, {err / band:.3f} of it), "
+          f"off-band sign mismatches {mism}", flush=True)
+    return err, band, mism
+
+
+def _gpu_solve(hjrlib, gpu, p, k, **opts):
+    torch = __import__("torch")
+    lt = torch.tensor(p.l, device=gpu)
+    kt = None if k is None else torch.tensor(k, device=gpu)
+    Vt = torch.empty_like(lt)
+    r, st = hjrlib.solve_device(p.grid, p.dyn, lt, kt, Vt, **opts)
+    torch.cuda.synchronize()
+    return Vt.cpu().numpy().reshape(p.grid.shape), r, st
+
+
+@pytest.fixture(scope="module")
+def dubins101(orc):
+    """Oracle solutions of the 101^3 Dubins problems (computed once for the module)."""
+    p = W.dubins_problem(101, dbar=0.1)
+    q = W.dubins_problem(101, dbar=0.05)
+    opts = orc.problem_opts(p)
+    print("[converged] oracle 101^3 Dubins solves (three, WENO5 + TVD-RK3) ...", flush=True)
+    K, ik = orc.solve(q.grid, q.dyn, q.l, **opts)
+    Vc, ic = orc.solve(p.grid, p.dyn, p.l, **opts)
+    Vw, iw = orc.solve(p.grid, p.dyn, p.l, K, **opts)
+    print(f"[converged] oracle steps: prior {ik['steps']}, cold {ic['steps']}, warm {iw['steps']}", flush=True)
+    assert ik["converged"] == ic["converged"] == iw["converged"] == 1
+    return p, K, Vc, Vw
+
+
+@pytest.mark.parametrize("warm", [False, True], ids=["cold", "warm"])
+def test_dubins101_fp32_polish_converged(gpu, hjrlib, dubins101, warm):
+    p, K, Vc, Vw = dubins101
+    opts = hjrlib.problem_options(p, precision=hjrlib.FP32_POLISH64, max_iter=20000)
+    V, r, st = _gpu_solve(hjrlib, gpu, p, K if warm else None, **opts)
+    assert st == hjrlib.OK
+    err, band, mism = _figures(f"dubins101 {'warm' if warm else 'cold'} FP32+polish "
+                               f"({r['iterations']}+{r['polish_iterations']} steps)", V, Vw if warm else Vc, p.l)
+    assert err <= band and mism == 0
+
+
+def test_dubins101_polish_start_against_the_solution(gpu, hjrlib, dubins101):
+    """Where the FP64 polish starts relative to the oracle's converged solution V*: the FP32
+    phase alone (same threshold, 3 FP32 spacings at max |l|) plus the polish shift 2 tol32.
+    The shift puts the start above V* except at a few nodes, where the FP32 iterate's own
+    distance to the FP64 fixed point (FP32 rounding of the scheme, not its stopping rule)
+    exceeds it: measured 66 of 1.03 M nodes, at most 1.2e-5 below, in the cold solve.  So the
+    start is not everywhere above V* (Theorem 2's premise); what is bounded is the deficit,
+    which stays far inside the tolerance band (the polished results then match the oracle, as
+    the tests above check)."""
+    p, K, Vc, Vw = dubins101
+    lmax = float(np.abs(p.l).max())
+    band = 1e-4 * lmax
+    ulp = 2.0 ** (np.frexp(lmax)[1] - 24)
+    tol32 = max(p.tol, 3 * ulp)
+    for k, Vo in ((None, Vc), (K, Vw)):
+        opts = hjrlib.problem_options(p, precision=hjrlib.FP32, tol_fp32=tol32, max_iter=20000)
+        V32, r, st = _gpu_solve(hjrlib, gpu, p, k, **opts)
+        start = np.minimum(p.l, V32 + 2 * tol32)
+        below = int(np.sum(start < Vo))
+        gap = float((start - Vo).min())
+        print(f"[converged] FP32 phase {'warm' if k is not None else 'cold'}: {r['iterations']} steps, "
+              f"polish start below V* at {below} of {p.grid.size} nodes, by at most {max(0.0, -gap):.3e} "
+              f"({max(0.0, -gap) / band:.3f} of the band)", flush=True)
+        assert below <= 1e-3 * p.grid.size
+        assert -gap <= 0.1 * band
+
+
+@pytest.fixture(scope="module")
+def quad9(orc):
+    p = W.quad6_problem(9, m=1.2, dbar=(0.5, 0.5, 0.5))
+    q = W.quad6_problem(9, m=1.2, dbar=(0.3, 0.3, 0.3))
+    opts = orc.problem_opts(p)
+    print("[converged] oracle 9^6 quadrotor solves ...", flush=True)
+    K, ik = orc.solve(q.grid, q.dyn, q.l, **opts)
+    Vc, ic = orc.solve(p.grid, p.dyn, p.l, **opts)
+    Vw, iw = orc.solve(p.grid, p.dyn, p.l, K, **opts)
+    print(f"[converged] oracle steps: prior {ik['steps']}, cold {ic['steps']}, warm {iw['steps']}", flush=True)
+    assert ik["converged"] == ic["converged"] == iw["converged"] == 1
+    return p, K, Vc, Vw
+
+
+@pytest.mark.parametrize("config", ["4", "-1"], ids=["flat", "march"])
+@pytest.mark.parametrize("warm", [False, True], ids=["cold", "warm"])
+def test_quad6_fp32_polish_converged(gpu, hjrlib, quad9, monkeypatch, warm, config):
+    p, K, Vc, Vw = quad9
+    monkeypatch.setenv("HJR_NPT", config)
+    opts = hjrlib.problem_options(p, precision=hjrlib.FP32_POLISH64, max_iter=20000)
+    V, r, st = _gpu_solve(hjrlib, gpu, p, K if warm else None, **opts)
+    assert st == hjrlib.OK
+    err, band, mism = _figures(f"quad6 9^6 {'warm' if warm else 'cold'} FP32+polish kernel {config} "
+                               f"({r['iterations']}+{r['polish_iterations']} steps)", V, Vw if warm else Vc, p.l)
+    assert err <= band and mism == 0
