@@ -219,6 +219,23 @@ hjr_status hjr_solve_device(const hjr_grid *grid, const hjr_dynamics *dyn, const
                             const double *k_dev, const hjr_options *opts, double *V_dev,
                             void *stream, hjr_result *result);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): hjr_solve_device without any allocation.  Same
+ * arguments, semantics and results (bitwise) as hjr_solve_device.  Every device buffer the
+ * solve needs (its FP32 and FP64 working arrays, tables, state and tile lists) is taken from a
+ * static 64 MiB block that each GPU holds from the library's load until the process ends, so
+ * no hipMalloc, hipFree, pinned host allocation, event, graph or stream is created; the caller
+ * still provides l_dev, k_dev and V_dev.  Limit: about 2 million grid points with TVD-RK3 and
+ * the FP64 polish (32 bytes per point), about 3 million with Euler; larger problems return
+ * HJR_ERR_BUDGET before any device work.  The block is shared by all calls on one GPU: calls
+ * from several host threads on the same GPU are serialised (one waits for the other), and
+ * nothing left in it by an earlier call is relied on.  No autotuning and no kernel profile run
+ * on this path (the tuner's earlier choices still apply).  `stream`: a hipStream_t, or NULL for
+ * the null stream. */
+hjr_status hjr_solve_device_noalloc(const hjr_grid *grid, const hjr_dynamics *dyn, const double *l_dev,
+                                    const double *k_dev, const hjr_options *opts, double *V_dev,
+                                    void *stream, hjr_result *result);
+
 /* Reach-avoid solve (the reach-avoid problems that Sec. II names beside reach and avoid): a
  * constraint function g (prod(n) doubles, finite, same layout as l) marks where the state may
  * not go (g > 0).  Every step ends with V <- max(g, min(l, V_step)) and the start is

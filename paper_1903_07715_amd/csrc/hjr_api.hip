@@ -25,6 +25,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -635,27 +636,49 @@ private:
 };
 
 // --------------------------------------------------------------------------------------------
+// Arena: device memory carved from one caller-provided block (a bump allocator that never
+// frees; the allocation-free entry point hands the engine its static scratch array this way).
+// --------------------------------------------------------------------------------------------
+
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0;
+    size_t used = 0;
+    hipError_t alloc(void **ptr, size_t bytes)
+    {
+        const size_t b = align256(bytes);
+        if (used + b > size) return hipErrorOutOfMemory;
+        *ptr = base + used;
+        used += b;
+        return hipSuccess;
+    }
+};
+
+// --------------------------------------------------------------------------------------------
 // Engine
 // --------------------------------------------------------------------------------------------
 
 class Engine {
 public:
-    explicit Engine(int capacity) : cap_(capacity) {}
+    // arena: take every device buffer from this block instead of the pool, keep host staging in
+    // pageable memory, and make no allocating call at all: no graphs, no events (so no profile
+    // and no autotuning; the tuner's earlier choices still apply), no stream of its own.
+    explicit Engine(int capacity, Arena *arena = nullptr) : cap_(capacity), arena_(arena) {}
     ~Engine() { release(); }
 
     hjr_status init(hipStream_t stream)
     {
         HJR_HIP(hipGetDevice(&device_));
-        if (stream) {
+        if (stream || arena_) {
             stream_ = stream;
         } else {
             HJR_HIP(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
             own_stream_ = true;
         }
-        HJR_HIP(Pool::get().alloc((void **)&d_states_, sizeof(SolveState) * cap_));
-        HJR_HIP(Pool::get().alloc((void **)&d_insts_, sizeof(Inst) * cap_));
-        HJR_HIP(hipHostMalloc((void **)&h_states_, sizeof(SolveState) * cap_, hipHostMallocDefault));
-        HJR_HIP(hipHostMalloc((void **)&h_insts_, sizeof(Inst) * cap_, hipHostMallocDefault));
+        HJR_HIP(dalloc((void **)&d_states_, sizeof(SolveState) * cap_));
+        HJR_HIP(dalloc((void **)&d_insts_, sizeof(Inst) * cap_));
+        HJR_HIP(halloc((void **)&h_states_, sizeof(SolveState) * cap_));
+        HJR_HIP(halloc((void **)&h_insts_, sizeof(Inst) * cap_));
         std::memset(h_insts_, 0, sizeof(Inst) * cap_);
         // idle slots: a frozen state so step_end skips them
         for (int i = 0; i < cap_; ++i) {
@@ -676,6 +699,10 @@ public:
         if (const char *at = getenv("HJR_AUTOTUNE")) autotune_ = atoi(at) != 0;
         if (const char *gr = getenv("HJR_GRAPHS")) graphs_ = atoi(gr) != 0;
         if (const char *pb = getenv("HJR_PLANE_BLOCK_BYTES")) plane_block_bytes_ = strtoull(pb, nullptr, 10);
+        if (arena_) {
+            graphs_ = false;
+            autotune_ = false;
+        }
         return HJR_OK;
     }
 
@@ -690,20 +717,20 @@ public:
         drop_graphs();
         for (Request *r : slots_)
             if (r) drop(r);
-        Pool::get().release(d_states_);
-        Pool::get().release(d_insts_);
-        Pool::get().release(d_tiles32_);
-        Pool::get().release(d_tiles64_);
-        Pool::get().release(d_mtiles_[0]);
-        Pool::get().release(d_mtiles_[1]);
+        dfree(d_states_);
+        dfree(d_insts_);
+        dfree(d_tiles32_);
+        dfree(d_tiles64_);
+        dfree(d_mtiles_[0]);
+        dfree(d_mtiles_[1]);
         d_states_ = nullptr;
         d_insts_ = nullptr;
         d_tiles32_ = d_tiles64_ = nullptr;
         d_mtiles_[0] = d_mtiles_[1] = nullptr;
         mtiles_cap_[0] = mtiles_cap_[1] = 0;
-        if (h_states_) (void)hipHostFree(h_states_);
-        if (h_insts_) (void)hipHostFree(h_insts_);
-        if (h_tiles_) (void)hipHostFree(h_tiles_);
+        hfree(h_states_);
+        hfree(h_insts_);
+        hfree(h_tiles_);
         h_states_ = nullptr;
         h_insts_ = nullptr;
         h_tiles_ = nullptr;
@@ -739,7 +766,7 @@ public:
         if (slot < 0) return fail(HJR_ERR_INVALID_ARG, "engine is full");
         Layout L = plan_layout(*r, own_io, own_io ? g_host != nullptr : r->g_dev != nullptr);
         r->bytes = L.total;
-        HJR_HIP(Pool::get().alloc(&r->mem, L.total));
+        HJR_HIP(dalloc(&r->mem, L.total));
         char *base = (char *)r->mem;
         if (own_io) {
             r->V_dev = (double *)(base + L.V64);
@@ -818,7 +845,7 @@ public:
             if (s != HJR_OK) return s;
         }
         const int ninst = top_slot_ + 1;
-        const bool prof = g_profile_on.load() != 0;
+        const bool prof = g_profile_on.load() != 0 && !arena_;
         nev_ = 0;
         // where each instance stood before the chunk, to tell working launches from the ones
         // issued after it finished (profile accounting)
@@ -1018,11 +1045,33 @@ public:
     // Return a request's working memory to the pool (after its output has been consumed).
     void drop(Request *r)
     {
-        if (r->mem) Pool::get().release(r->mem);
+        dfree(r->mem);
         r->mem = nullptr;
     }
 
 private:
+    // device and host buffers: the pool and pinned host memory, or the arena and plain host
+    // memory (an arena never frees; its block is reused by the next engine)
+    hipError_t dalloc(void **p, size_t bytes) { return arena_ ? arena_->alloc(p, bytes) : Pool::get().alloc(p, bytes); }
+    void dfree(void *p)
+    {
+        if (!arena_) Pool::get().release(p);
+    }
+    hipError_t halloc(void **p, size_t bytes)
+    {
+        if (!arena_) return hipHostMalloc(p, bytes, hipHostMallocDefault);
+        *p = ::operator new(bytes, std::nothrow);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    void hfree(void *p)
+    {
+        if (!p) return;
+        if (arena_)
+            ::operator delete(p);
+        else
+            (void)hipHostFree(p);
+    }
+
     struct EvRec {
         hipEvent_t a, b;
         int prec, stage;
@@ -1215,10 +1264,10 @@ private:
         // earlier copies from the staging buffer, and kernels reading the old list, must be done
         HJR_HIP(hipStreamSynchronize(stream_));
         if (need > mtiles_cap_[p]) {
-            Pool::get().release(d_mtiles_[p]);
+            dfree(d_mtiles_[p]);
             d_mtiles_[p] = nullptr;
             mtiles_cap_[p] = std::max(need * 2, (size_t)4096);
-            HJR_HIP(Pool::get().alloc((void **)&d_mtiles_[p], mtiles_cap_[p]));
+            HJR_HIP(dalloc((void **)&d_mtiles_[p], mtiles_cap_[p]));
         }
         HJR_HIP(hipMemcpy(d_mtiles_[p], m.data(), need, hipMemcpyHostToDevice));
         return HJR_OK;
@@ -1229,13 +1278,13 @@ private:
         const size_t need = (a.size() + b.size() + 2) * sizeof(Tile);
         if (need > tiles_cap_) {
             HJR_HIP(hipStreamSynchronize(stream_));
-            Pool::get().release(d_tiles32_);
-            Pool::get().release(d_tiles64_);
-            if (h_tiles_) (void)hipHostFree(h_tiles_);
+            dfree(d_tiles32_);
+            dfree(d_tiles64_);
+            hfree(h_tiles_);
             tiles_cap_ = std::max(need * 2, (size_t)4096);
-            HJR_HIP(Pool::get().alloc((void **)&d_tiles32_, tiles_cap_));
-            HJR_HIP(Pool::get().alloc((void **)&d_tiles64_, tiles_cap_));
-            HJR_HIP(hipHostMalloc((void **)&h_tiles_, tiles_cap_ * 2, hipHostMallocDefault));
+            HJR_HIP(dalloc((void **)&d_tiles32_, tiles_cap_));
+            HJR_HIP(dalloc((void **)&d_tiles64_, tiles_cap_));
+            HJR_HIP(halloc((void **)&h_tiles_, tiles_cap_ * 2));
         }
         // staging is reused: earlier copies from it must have completed
         HJR_HIP(hipStreamSynchronize(stream_));
@@ -1309,6 +1358,7 @@ private:
     int npt_override_ = 0;
 
     int cap_;
+    Arena *arena_ = nullptr;
     int device_ = 0;
     int cus_ = 256;
     hipStream_t stream_ = nullptr;
@@ -1644,6 +1694,84 @@ static hjr_status solve_dev(const hjr_grid *grid, const hjr_dynamics *dyn, const
     r.g_dev = g_dev;
     r.V_dev = V_dev;
     Engine E(1);
+    s = E.init((hipStream_t)stream);
+    if (s != HJR_OK) return s;
+    std::vector<Request *> reqs{&r};
+    s = run_all(E, reqs, false, {}, {}, opts->steps_per_sync);
+    E.drop(&r);
+    if (s != HJR_OK) return s;
+    if (result) *result = r.result;
+    return r.status;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Allocation-free solve.  Its engine takes every device buffer from `scratch`, a file-scope
+// device array of kScratchBytes that each GPU holds from the library's load until the process
+// ends.  In host code the array's name is only a stand-in: the device address of each GPU's
+// copy comes from hipGetSymbolAddress with that GPU current, once, and is kept per device.
+// Calls on one GPU share its copy, so they are serialised by a per-device mutex; the contents
+// left by the last call are never relied on (every buffer is written before it is read).
+// ---------------------------------------------------------------------------------------------
+
+namespace hjr {
+constexpr size_t kScratchBytes = 64ull << 20;
+constexpr int kMaxScratchDevices = 64;
+}  // namespace hjr
+static __device__ __align__(256) unsigned char scratch[hjr::kScratchBytes];
+namespace hjr {
+static std::mutex g_scratch_mu[kMaxScratchDevices];
+static void *g_scratch_ptr[kMaxScratchDevices];
+
+// The current device's scratch address (the caller holds g_scratch_mu[dev]).
+static hjr_status scratch_address(int dev, void **out)
+{
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(HJR_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return HJR_OK;
+}
+
+// Scratch bytes a single solve's engine may take: the state and descriptor, the request's
+// working arrays, and the flat and march tile lists of both precisions (the engine keeps room
+// for twice the tiles it lists; the bound takes one tile per 256 nodes, the most any
+// configuration lists, plus padding of the march order).
+static size_t noalloc_bytes(const Request &r)
+{
+    const size_t tiles = (size_t)((r.npts + kBlock - 1) / kBlock) + 8 * kBlock;
+    const size_t list = align256(std::max(2 * tiles * sizeof(MTile), (size_t)4096));
+    return align256(sizeof(SolveState)) + align256(sizeof(Inst)) + request_bytes(r, false) + 4 * list;
+}
+}  // namespace hjr
+
+hjr_status hjr_solve_device_noalloc(const hjr_grid *grid, const hjr_dynamics *dyn, const double *l_dev,
+                                    const double *k_dev, const hjr_options *opts, double *V_dev, void *stream,
+                                    hjr_result *result)
+{
+    Request r;
+    hjr_status s = prepare(r, grid, dyn, opts, k_dev);
+    if (s != HJR_OK) return s;
+    if (!l_dev || !V_dev) return fail(HJR_ERR_INVALID_ARG, "l_dev and V_dev must not be NULL");
+    const size_t need = noalloc_bytes(r);
+    if (need > kScratchBytes)
+        return fail(HJR_ERR_BUDGET, "the problem needs %zu bytes of scratch memory; the allocation-free entry point "
+                    "has %zu (use hjr_solve_device)", need, kScratchBytes);
+    int dev = 0;
+    HJR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(HJR_ERR_DEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> guard(g_scratch_mu[dev]);
+    void *base = nullptr;
+    s = scratch_address(dev, &base);
+    if (s != HJR_OK) return s;
+    r.l_dev = l_dev;
+    r.k_dev = k_dev;
+    r.V_dev = V_dev;
+    Arena arena{(char *)base, kScratchBytes, 0};
+    Engine E(1, &arena);
     s = E.init((hipStream_t)stream);
     if (s != HJR_OK) return s;
     std::vector<Request *> reqs{&r};

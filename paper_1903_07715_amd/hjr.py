@@ -27,7 +27,8 @@ FP64, FP32, FP32_POLISH64 = 0, 1, 2
 CONV_PER_STEP, CONV_PER_INTERVAL = 0, 1
 
 EXPORTED = ["hjr_abi_version", "hjr_build_id", "hjr_default_options", "hjr_status_string", "hjr_last_error",
-            "hjr_device_count", "hjr_solve", "hjr_solve_device", "hjr_batch_solve", "hjr_cfl_dt",
+            "hjr_device_count", "hjr_solve", "hjr_solve_device", "hjr_solve_device_noalloc", "hjr_batch_solve",
+            "hjr_cfl_dt",
             "hjr_stage_device", "hjr_ctx_create", "hjr_submit", "hjr_poll", "hjr_ctx_drain",
             "hjr_ctx_get_stats", "hjr_ctx_destroy", "hjr_profile_enable", "hjr_profile_read",
             "hjr_num_controls", "hjr_gradient_device", "hjr_safe_control_device", "hjr_solve_reach_avoid",
@@ -116,6 +117,7 @@ def load():
         lib.hjr_num_controls.restype = C.c_int32
         lib.hjr_solve.argtypes = [P(Grid_), P(Dynamics_), dp, dp, P(Options_), dp, P(Result_)]
         lib.hjr_solve_device.argtypes = [P(Grid_), P(Dynamics_), vp, vp, P(Options_), vp, vp, P(Result_)]
+        lib.hjr_solve_device_noalloc.argtypes = [P(Grid_), P(Dynamics_), vp, vp, P(Options_), vp, vp, P(Result_)]
         lib.hjr_solve_reach_avoid.argtypes = [P(Grid_), P(Dynamics_), dp, dp, dp, P(Options_), dp, P(Result_)]
         lib.hjr_solve_reach_avoid_device.argtypes = [P(Grid_), P(Dynamics_), vp, vp, vp, P(Options_), vp, vp,
                                                      P(Result_)]
@@ -291,6 +293,22 @@ def solve_device(grid, dyn, l_dev, k_dev, V_dev, stream=None, constraint=None, *
     else:
         st = load().hjr_solve_reach_avoid_device(gs, ds, _tptr(l_dev), _tptr(constraint), _tptr(k_dev), C.byref(o),
                                                  _tptr(V_dev), _stream_ptr(stream), C.byref(res))
+    _check(st)
+    return result_dict(res), st
+
+
+def solve_device_noalloc(grid, dyn, l_dev, k_dev, V_dev, stream=None, **opts):
+    """hjr_solve_device_noalloc: hjr_solve_device on torch FP64 device tensors without any
+    device allocation (the library's static scratch block; see include/hjr.h for the limit).
+    Returns (result dict, status)."""
+    n = grid.size
+    _device_array(l_dev, "l", n)
+    _device_array(k_dev, "k", n, optional=True)
+    _device_array(V_dev, "V", n)
+    res = Result_()
+    o = options(**opts)
+    st = load().hjr_solve_device_noalloc(C.byref(grid_struct(grid)), C.byref(dyn_struct(dyn)), _tptr(l_dev),
+                                         _tptr(k_dev), C.byref(o), _tptr(V_dev), _stream_ptr(stream), C.byref(res))
     _check(st)
     return result_dict(res), st
 
