@@ -42,10 +42,11 @@ BYTES_PER_NODE_STEP_EULER_FP64 = 24
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (packed FMA) peak
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of the FP32 stage kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-# (scaled by a 1 GiB copy calibration), keyed by a hash of the kernel sources they were taken
-# from: a kernel changed since then reports null.
-MEASURED_TRAFFIC = {"113addb4c08e4d77": 9.893e6 + 3.923e6}
+# Bytes per launch of the headline's FP32 stage kernel (the plane-march kernel on the 25^6
+# quadrotor) between L2 and memory, from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a
+# 1 GiB copy calibration (profiles/quad6_25_headline_hbm_counters.txt), keyed by a hash of the
+# kernel sources they were taken from: a kernel changed since then reports null.
+MEASURED_TRAFFIC = {"64f7cb3e3e1eb022": {"quad6": 4.977e9 + 1.071e9}}
 
 
 def kernel_source_hash() -> str:
@@ -71,11 +72,12 @@ def parse():
     ap.add_argument("--polish-shift", type=float, default=-1.0, help="FP64 polish start shift (< 0: automatic)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["quad6", "dubins", "batch", "serve", "control", "quad10", "hbm",
+    ap.add_argument("--workload", choices=["quad6", "dubins", "unicycle", "batch", "serve", "control", "quad10", "hbm",
                                            "discount", "local"],
                     default="quad6",
                     help="quad6: the headline, warm-started FP32 + FP64-polish solves of the 25^6 quadrotor; "
                          "dubins: warm-started solves of the 101^3 Dubins car (WENO5 + TVD-RK3); "
+                         "unicycle: the 61^4 unicycle after one of its two obstacles moves, cold vs warm; "
                          "batch: the 64-instance mixed batch; "
                          "serve: a Poisson request stream through the serving context, warm vs cold; "
                          "control: safe-control queries against the converged 101^3 Dubins value function; "
@@ -161,6 +163,8 @@ def main():
         return
     if args.workload == "quad6":
         return bench_quad6(args)
+    if args.workload == "unicycle":
+        return bench_unicycle(args)
     return bench_dubins(args)
 
 
@@ -289,7 +293,8 @@ def bench_quad6(args):
     gbs32 = BYTES_PER_NODE_STEP_EULER_FP32 * npts / avg32 / 1e9
     gbs64 = BYTES_PER_NODE_STEP_EULER_FP64 * npts / avg64 / 1e9
     roofline = {"bound": "hbm", "achieved": round(gbs32, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(gbs32 / PEAK_HBM_GBS, 4), "traffic": MEASURED_TRAFFIC.get(kernel_source_hash()),
+                "frac": round(gbs32 / PEAK_HBM_GBS, 4),
+                "traffic": MEASURED_TRAFFIC.get(kernel_source_hash(), {}).get("quad6") if n == 25 else None,
                 "kernel": "march_kernel<float, Quad6> (upwind + Lax-Friedrichs + Euler step, FP32)",
                 "bytes_per_update": BYTES_PER_NODE_STEP_EULER_FP32,
                 "avg_launch_us": round(avg32 * 1e6, 1), "working_launches": n32,
@@ -337,6 +342,54 @@ def bench_quad6(args):
 
         line["cpu_baseline"], line["parity"] = cpu_baseline_quad6(p, q, args.parity_n, gpu_solve)
     print(json.dumps(line), flush=True)
+
+
+def bench_unicycle(args):
+    """The 4-D unicycle on 61^4 (13.8 M nodes) among two seeded disks; one disk moves by 0.3 and
+    the value function is recomputed cold and warm-started from the one before the move (neither
+    obstacle set contains the other, so Theorem 1 promises only a conservative result: the warm
+    unsafe set contains the cold one).  First-order upwind + Euler, FP32 + FP64 polish, solved to
+    convergence (WENO5 + TVD-RK3, the configuration's scheme, has no steady state here; its
+    fixed-step parity is tested).  Reports steps, statuses, solves/s and the set containment."""
+    import numpy as np
+    import torch
+
+    from paper_1903_07715_amd import hjr
+    from paper_1903_07715_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    old = W.unicycle_problem(61)
+    new = W.unicycle_problem(61, moved=True)
+    for p in (old, new):
+        p.spatial, p.temporal, p.cfl = 1, 1, 0.8
+    opts = hjr.problem_options(new, precision=hjr.FP32_POLISH64, max_iter=100000)
+    lo, ln = torch.tensor(old.l, device=dev), torch.tensor(new.l, device=dev)
+    K = torch.empty_like(lo)
+    r0, s0 = hjr.solve_device(old.grid, old.dyn, lo, None, K, **opts)
+    log(f"unicycle 61^4 before the move: {r0['iterations']}+{r0['polish_iterations']} steps, status {s0}")
+    out = {"workload": "unicycle4-61^4-two-disks-move0.3-upwind-euler-fp32-polish64", "nodes": new.grid.size,
+           "prior": {"steps": [r0["iterations"], r0["polish_iterations"]], "status": s0, "seconds": r0["seconds"]}}
+    Vs = {}
+    for warm in (False, True):
+        V = torch.empty_like(ln)
+        hjr.solve_device(new.grid, new.dyn, ln, K if warm else None, V, **opts)  # untimed (tuning)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r, st = hjr.solve_device(new.grid, new.dyn, ln, K if warm else None, V, **opts)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / args.steps
+        Vs[warm] = V.cpu().numpy()
+        key = "warm" if warm else "cold"
+        out[key] = {"seconds": el, "solves_per_s": 1.0 / el, "steps": [r["iterations"], r["polish_iterations"]],
+                    "status": st}
+        log(f"{key}: {out[key]}")
+    band = 1e-4 * float(np.abs(new.l).max())
+    out["warm_over_cold"] = out["cold"]["seconds"] / out["warm"]["seconds"]
+    out["max_abs_warm_minus_cold"] = float(np.abs(Vs[True] - Vs[False]).max())
+    out["cold_unsafe_nodes_not_unsafe_warm"] = int(np.sum((Vs[False] < -band) & (Vs[True] > 0)))
+    out["unsafe_nodes"] = {"cold": int(np.sum(Vs[False] <= 0)), "warm": int(np.sum(Vs[True] <= 0))}
+    print(json.dumps(out), flush=True)
 
 
 def bench_dubins(args):
@@ -426,7 +479,7 @@ def bench_dubins(args):
     achieved_tflops = flops / avg_s / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
-                "traffic": MEASURED_TRAFFIC.get(kernel_source_hash()),
+                "traffic": MEASURED_TRAFFIC.get(kernel_source_hash(), {}).get("dubins") if n == 101 else None,
                 "kernel": "stage_kernel_one<float, Dubins, WENO5> (WENO5 + LF + TVD-RK3 stage)",
                 "avg_launch_us": round(avg_s * 1e6, 2), "working_launches": launches,
                 "algorithmic_gbs": round(BYTES_PER_NODE_STEP_RK3_FP32 / 3 * npts / avg_s / 1e9, 1)}
