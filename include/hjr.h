@@ -63,7 +63,7 @@
 extern "C" {
 #endif
 
-#define HJR_ABI_VERSION 4
+#define HJR_ABI_VERSION 5
 #define HJR_MAX_DIM 6
 #define HJR_MAX_PARAMS 16
 

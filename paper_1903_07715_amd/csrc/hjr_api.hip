@@ -296,6 +296,10 @@ struct Request {
     int64_t ticket = 0;
     double t_submit = 0.0, t_start = 0.0;
     bool done = false;
+    // march tiles of this request in its slot, for runs of mtiles_len planes (-1: none built);
+    // kept across engine rebuilds, which happen at every admission, hand-over and completion
+    std::vector<MTile> mtiles;
+    int mtiles_len = -1;
 };
 
 static void make_constants(const hjr_dynamics &dy, double c[8])
@@ -520,16 +524,21 @@ static SolveState initial_state(const Request &r)
 // --------------------------------------------------------------------------------------------
 
 // Launch configurations: 1, 2, 4, 8 = flat tiles with that many nodes per thread; kMarchFull =
-// the plane-march kernel over whole dim-0 lines, kMarch8 = the same in runs of 8 planes (more
-// threads, two extra loads per run).  The march kernel serves first-order upwind groups whose
-// dim-0 planes hold enough columns to fill the device.
+// the plane-march kernel over whole dim-0 lines, -8, -4, -2 = the same in runs of that many
+// planes (more threads; per run, the planes before and after it are read again: two extra loads
+// for upwind, six and one extra dim-0 interface for WENO5).  The march kernels serve groups whose
+// dim-0 planes hold enough columns to fill the device at one thread per column.
 static const int kMarchFull = -1;
 static const int kMarch8 = -8;
 static const int kFlatSchedule[] = {4, 2, 8, 1, 4};
 static const int kMarchSchedule[] = {4, kMarchFull, 2, 8, 1, kMarch8, 4};
+static const int kMarchW5Schedule[] = {4, -4, 2, -2, 8, kMarch8, 1, kMarchFull, 4};
 static const uint64_t kMarchMinColumns = 8192;
 
-static bool valid_config(int c) { return c == 1 || c == 2 || c == 4 || c == 8 || c == kMarchFull || c == kMarch8; }
+static bool valid_config(int c)
+{
+    return c == 1 || c == 2 || c == 4 || c == 8 || c == kMarchFull || c == -2 || c == -4 || c == kMarch8;
+}
 static bool is_march(int c) { return c < 0; }
 
 class Tuner {
@@ -551,6 +560,10 @@ public:
     static bool march_key(const std::string &k) { return k.size() > 2 && k.compare(k.size() - 2, 2, "_m") == 0; }
     static const int *schedule(const std::string &k, int *len)
     {
+        if (march_key(k) && k.find("_sp5_") != std::string::npos) {
+            *len = (int)(sizeof kMarchW5Schedule / sizeof kMarchW5Schedule[0]);
+            return kMarchW5Schedule;
+        }
         if (march_key(k)) {
             *len = (int)(sizeof kMarchSchedule / sizeof kMarchSchedule[0]);
             return kMarchSchedule;
@@ -1160,7 +1173,8 @@ private:
             g.nodes += r->npts;
             g.largest = std::max(g.largest, r->npts);
             g.min_cols = std::min(g.min_cols, r->npts / (uint64_t)r->grid.n[0]);
-            g.march_ok = g.march_ok && r->opts.spatial == HJR_UPWIND1 && r->grid.ndim >= 2 && !r->inst.act;
+            g.march_ok = g.march_ok && (r->opts.spatial == HJR_UPWIND1 || r->opts.spatial == HJR_WENO5) &&
+                         r->grid.ndim >= 2 && !r->inst.act;
         }
         if (top_slot_ < 0) top_slot_ = 0;
         std::vector<Tile> t[2];
@@ -1190,10 +1204,10 @@ private:
                         if (!cfg) cfg = kFusedNpt;
                     }
                 }
-                // flat tiles of every group (the interval kernel walks them); march groups also
-                // get their march tiles
+                // flat tiles of the groups launched with them, and of every group when the
+                // interval kernel (which walks them) runs; march groups get their march tiles
                 const int off = (int)t[p].size();
-                append_tiles(kv.second.slots, is_march(cfg) ? 4 : cfg, t[p]);
+                if (!is_march(cfg) || any_interval_) append_tiles(kv.second.slots, is_march(cfg) ? 4 : cfg, t[p]);
                 const int moff = (int)mt[p].size();
                 if (is_march(cfg)) append_march_tiles(kv.second.slots, cfg == kMarchFull ? 0 : -cfg, mt[p]);
                 segs_[p].push_back(Seg{dyn, sp, cfg, off, (int)t[p].size() - off, moff, (int)mt[p].size() - moff,
@@ -1252,8 +1266,13 @@ private:
     void append_march_tiles(const std::vector<int> &slots, int len, std::vector<MTile> &out)
     {
         for (int i : slots) {
-            const Request *r = slots_[i];
-            march_tiles(i, r->grid.ndim, r->grid.n, len, out);
+            Request *r = slots_[i];
+            if (r->mtiles_len != len) {
+                r->mtiles.clear();
+                march_tiles(i, r->grid.ndim, r->grid.n, len, r->mtiles);
+                r->mtiles_len = len;
+            }
+            out.insert(out.end(), r->mtiles.begin(), r->mtiles.end());
         }
     }
 
@@ -1303,9 +1322,9 @@ private:
     hjr_status launch_stage_all(int prec, int stage, bool prof)
     {
         const int nt = prec ? n64_ : n32_;
-        if (nt <= 0) return HJR_OK;
         const Tile *tl = prec ? d_tiles64_ : d_tiles32_;
         if (fused_) {
+            if (nt <= 0) return HJR_OK;
             hipEvent_t a = nullptr, b = nullptr;
             if (prof) {
                 hjr_status s = event_pair(&a, &b, prec, stage, nodes_[prec], -1);
@@ -1319,8 +1338,10 @@ private:
         }
         // per-group kernel durations (profile, or the autotuner's timing of a candidate) come
         // from events stamped by the launch itself with the kernel's start and end
+        // (march groups have no flat tiles unless the interval kernel needs them)
         for (int gi = 0; gi < (int)segs_[prec].size(); ++gi) {
             const Seg &g = segs_[prec][gi];
+            if ((is_march(g.npt) ? g.mcount : g.count) <= 0) continue;
             const bool explore = !g.tune_key.empty() && !prof;
             hipEvent_t ga = nullptr, gb = nullptr;
             if (prof || explore) {
@@ -1328,7 +1349,7 @@ private:
                 if (s != HJR_OK) return s;
             }
             if (is_march(g.npt))
-                HJR_HIP(launch_march(prec != 0, g.dyn, d_insts_, d_mtiles_[prec] + g.moff, g.mcount, stage, stream_,
+                HJR_HIP(launch_march(prec != 0, g.dyn, g.spatial, d_insts_, d_mtiles_[prec] + g.moff, g.mcount, stage, stream_,
                                      ga, gb));
             else
                 HJR_HIP(launch_stage_one(prec != 0, g.dyn, g.spatial, g.npt, d_insts_, tl + g.off, g.count, stage,
@@ -1340,7 +1361,7 @@ private:
 
     struct Seg {
         int dyn, spatial;
-        int npt;               // launch configuration: nodes per thread, or kMarchFull / kMarch8
+        int npt;               // launch configuration: nodes per thread, or a march run length (< 0)
         int off, count;        // flat tiles
         int moff, mcount;      // march tiles
         int64_t nodes;         // nodes of the group's instances
@@ -1994,7 +2015,7 @@ hjr_status hjr_stage_device(const hjr_grid *grid, const hjr_dynamics *dyn, int32
     if (const char *np = getenv("HJR_NPT")) npt = atoi(np);
     if (!valid_config(npt)) npt = 0;
     const uint64_t cols = r.npts / (uint64_t)grid->n[0];
-    const bool march_ok = spatial == HJR_UPWIND1 && grid->ndim >= 2 && cols >= kMarchMinColumns &&
+    const bool march_ok = (spatial == HJR_UPWIND1 || spatial == HJR_WENO5) && grid->ndim >= 2 && cols >= kMarchMinColumns &&
                           r.npts * (f32 ? 4ull : 8ull) <= 0xffffffffull;
     if (is_march(npt) && !march_ok) npt = 0;
     if (!npt) npt = Tuner::get().choice(Tuner::key(f32 ? 0 : 1, dyn->id, spatial, r.npts, march_ok));
@@ -2017,7 +2038,7 @@ hjr_status hjr_stage_device(const hjr_grid *grid, const hjr_dynamics *dyn, int32
     if (e == hipSuccess) e = hipMemcpyAsync(dtl, tl_host, tl_bytes, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
         if (is_march(npt))
-            e = launch_march(!f32, dyn->id, dinst, (const MTile *)dtl, (int)mtiles.size(), k, st);
+            e = launch_march(!f32, dyn->id, spatial, dinst, (const MTile *)dtl, (int)mtiles.size(), k, st);
         else if (fused)
             e = launch_stage(!f32, dinst, (const Tile *)dtl, (int)tiles.size(), k, 0, st);
         else

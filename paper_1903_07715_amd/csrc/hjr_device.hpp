@@ -211,64 +211,88 @@ __device__ __forceinline__ void stg(T *p, uint32_t i, T v)
 
 // ---------------------------------------------------------------------------------------------
 // WENO5 one-sided derivatives (Jiang-Peng smoothness indicators, ideal weights 0.1/0.6/0.3,
-// eps = 1e-6 max v^2 + 1e-18 over the five differences v of the stencil) at a node, from its six
-// undivided first differences d[k] = u(k-2) - u(k-3) (offsets k-2): D- from (d0..d4), D+ from
-// the mirrored (d5..d1).  Both come out multiplied by dx.
+// eps = 1e-6 max v^2 + 1e-18 over the five differences v of the stencil), formed per interface.
+// The interface between nodes j and j+1 has the five undivided first differences
+// e1..e5 = u(j-1) - u(j-2), ..., u(j+3) - u(j+2).  D- at node j+1 takes v = (e1..e5) and D+ at
+// node j the mirrored v = (e5..e1); the mirrored stencil has the same three indicators in reverse
+// order (A, B, C over (e1,e2,e3), (e2,e3,e4), (e3,e4,e5)) and the same eps, so everything but
+// the candidate values is computed once per interface and serves both derivatives.  Both come
+// out multiplied by dx.
 // The weights depend only on the ratios of the (S_k + eps), so every S_k and eps may carry one
 // common factor: with undivided differences and a factor 4 the indicators are
-// S_k = (13/3) c_k^2 + r_k^2 and eps = 4e-6 max d^2 + 4e-18 dx^2 (eps0).  The two derivatives
-// share the second differences c centred at offsets -1, 0, 1, 2 and four of the five squares in
-// eps.  With a_k = g_k / (S_k + eps)^2, the normalised combination sum a_k phi_k / sum a_k is
-// formed without the a_k: t_k = (S_k + eps) 2^-e (e the exponent of eps) lies in [1, 7e7], and
-// a_k is proportional to g_k prod_{j != k} t_j^2, which stays inside the FP32 range; the ideal
-// weights are folded in as 0.1 : 0.6 : 0.3 = 1 : 6 : 3, with 6 phi_2 and 3 phi_3 formed
-// directly, so one reciprocal finishes the derivative.
+// S_k = (13/3) c_k^2 + r_k^2 and eps = 4e-6 max e^2 + 4e-18 dx^2 (eps0).  With
+// a_k = g_k / (S_k + eps)^2, the normalised combination sum a_k phi_k / sum a_k is formed without
+// the a_k: t_k = (S_k + eps) 2^-x (x the exponent of eps) lies in [1, 7e7], and a_k is
+// proportional to g_k prod_{i != k} t_i^2, which stays inside the FP32 range; so the interface
+// keeps the three pair products of the t_k^2.  The ideal weights are folded in as
+// 0.1 : 0.6 : 0.3 = 1 : 6 : 3, with 6 phi_2 and 3 phi_3 formed directly, so one reciprocal
+// finishes each derivative.
 // ---------------------------------------------------------------------------------------------
+template <typename T> struct WenoIf {
+    T ab, ac, bc;  // t_A^2 t_B^2, t_A^2 t_C^2, t_B^2 t_C^2
+};
+
+// The WENO5 arithmetic below is written with explicit fused multiply-adds and contraction off,
+// so its rounding is fixed by the source alone: the flat kernel (both interfaces of every node)
+// and the march kernel (each interface once, shared by two nodes) produce the same bits.
 template <typename T>
-__device__ __forceinline__ T weno5_combine(T S1, T S2, T S3, T eps, T f1, T f6, T f3)
+__device__ __forceinline__ WenoIf<T> weno5_interface(T e1, T e2, T e3, T e4, T e5, T eps0)
 {
+#pragma clang fp contract(off)
+    const T k = T(13.0 / 3.0);
+    const T cA = fma(T(-2), e2, e1) + e3;
+    const T cB = fma(T(-2), e3, e2) + e4;
+    const T cC = fma(T(-2), e4, e3) + e5;
+    const T rA = fma(T(3), e3, fma(T(-4), e2, e1));
+    const T rB = e2 - e4;
+    const T rC = fma(T(3), e3, fma(T(-4), e4, e5));
+    const T SA = fma(k * cA, cA, rA * rA);
+    const T SB = fma(k * cB, cB, rB * rB);
+    const T SC = fma(k * cC, cC, rC * rC);
+    const T m = fmax(fmax(fmax(e2 * e2, e3 * e3), e4 * e4), fmax(e1 * e1, e5 * e5));
+    const T eps = fma(T(4e-6), m, eps0);
     const T sc = pow2_recip(eps);
     const T e = eps * sc;
-    const T t1 = S1 * sc + e, t2 = S2 * sc + e, t3 = S3 * sc + e;
-    const T s1 = t1 * t1, s2 = t2 * t2, s3 = t3 * t3;
-    const T p23 = s2 * s3, p13 = s1 * s3, p12 = s1 * s2;
-    return (p23 * f1 + p13 * f6 + p12 * f3) * recip(p23 + T(6) * p13 + T(3) * p12);
+    const T tA = fma(SA, sc, e), tB = fma(SB, sc, e), tC = fma(SC, sc, e);
+    const T sA = tA * tA, sB = tB * tB, sC = tC * tC;
+    return WenoIf<T>{sA * sB, sA * sC, sB * sC};
 }
 
+// D- at the node right of the interface: v = (e1..e5), weights 1 : 6 : 3 on A, B, C.
+template <typename T>
+__device__ __forceinline__ T weno5_left(const WenoIf<T> &w, T e1, T e2, T e3, T e4, T e5)
+{
+#pragma clang fp contract(off)
+    const T f1 = fma(e3, T(11.0 / 6.0), fma(e2, T(-7.0 / 6.0), e1 * T(1.0 / 3.0)));
+    const T f6 = fma(T(2), e4, fma(T(5), e3, -e2));
+    const T f3 = fma(T(-0.5), e5, fma(T(2.5), e4, e3));
+    const T num = fma(w.ab, f3, fma(w.ac, f6, w.bc * f1));
+    const T den = fma(T(3), w.ab, fma(T(6), w.ac, w.bc));
+    return num * recip(den);
+}
+
+// D+ at the node left of the interface: v = (e5..e1), weights 1 : 6 : 3 on C, B, A.
+template <typename T>
+__device__ __forceinline__ T weno5_right(const WenoIf<T> &w, T e1, T e2, T e3, T e4, T e5)
+{
+#pragma clang fp contract(off)
+    const T f1 = fma(e3, T(11.0 / 6.0), fma(e4, T(-7.0 / 6.0), e5 * T(1.0 / 3.0)));
+    const T f6 = fma(T(2), e2, fma(T(5), e3, -e4));
+    const T f3 = fma(T(-0.5), e1, fma(T(2.5), e2, e3));
+    const T num = fma(w.bc, f3, fma(w.ac, f6, w.ab * f1));
+    const T den = fma(T(3), w.bc, fma(T(6), w.ac, w.ab));
+    return num * recip(den);
+}
+
+// D- and D+ at a node from its six differences d[k] = u(k-2) - u(k-3): D- from the interface on
+// its left (d0..d4), D+ from the one on its right (d1..d5).
 template <typename T>
 __device__ __forceinline__ void weno5_pair(const T *d, T eps0, T &dm, T &dp)
 {
-    const T k = T(13.0 / 3.0);
-    const T c1 = d[0] - T(2) * d[1] + d[2];
-    const T c2 = d[1] - T(2) * d[2] + d[3];
-    const T c3 = d[2] - T(2) * d[3] + d[4];
-    const T c4 = d[3] - T(2) * d[4] + d[5];
-    const T q1 = (k * c1) * c1, q2 = (k * c2) * c2, q3 = (k * c3) * c3, q4 = (k * c4) * c4;
-    const T mid = fmax(fmax(d[1] * d[1], d[2] * d[2]), fmax(d[3] * d[3], d[4] * d[4]));
-    // D-: v = (d0, d1, d2, d3, d4); phi_1, 6 phi_2, 3 phi_3 of the three candidate stencils
-    {
-        const T r1 = d[0] - T(4) * d[1] + T(3) * d[2];
-        const T r2 = d[1] - d[3];
-        const T r3 = T(3) * d[2] - T(4) * d[3] + d[4];
-        const T S1 = r1 * r1 + q1, S2 = r2 * r2 + q2, S3 = r3 * r3 + q3;
-        const T eps = T(4e-6) * fmax(mid, d[0] * d[0]) + eps0;
-        const T f1 = d[0] * T(1.0 / 3.0) - d[1] * T(7.0 / 6.0) + d[2] * T(11.0 / 6.0);
-        const T f6 = T(5) * d[2] - d[1] + T(2) * d[3];
-        const T f3 = d[2] + T(2.5) * d[3] - T(0.5) * d[4];
-        dm = weno5_combine(S1, S2, S3, eps, f1, f6, f3);
-    }
-    // D+: v = (d5, d4, d3, d2, d1)
-    {
-        const T r1 = d[5] - T(4) * d[4] + T(3) * d[3];
-        const T r2 = d[4] - d[2];
-        const T r3 = T(3) * d[3] - T(4) * d[2] + d[1];
-        const T S1 = r1 * r1 + q4, S2 = r2 * r2 + q3, S3 = r3 * r3 + q2;
-        const T eps = T(4e-6) * fmax(mid, d[5] * d[5]) + eps0;
-        const T f1 = d[5] * T(1.0 / 3.0) - d[4] * T(7.0 / 6.0) + d[3] * T(11.0 / 6.0);
-        const T f6 = T(5) * d[3] - d[4] + T(2) * d[2];
-        const T f3 = d[3] + T(2.5) * d[2] - T(0.5) * d[1];
-        dp = weno5_combine(S1, S2, S3, eps, f1, f6, f3);
-    }
+    const WenoIf<T> wl = weno5_interface(d[0], d[1], d[2], d[3], d[4], eps0);
+    const WenoIf<T> wr = weno5_interface(d[1], d[2], d[3], d[4], d[5], eps0);
+    dm = weno5_left(wl, d[0], d[1], d[2], d[3], d[4]);
+    dp = weno5_right(wr, d[1], d[2], d[3], d[4], d[5]);
 }
 
 // Every lane of a block works on one tile of one instance, so the instance's array pointers are
@@ -314,18 +338,17 @@ __device__ __forceinline__ void line_load(const T *__restrict__ S, uint32_t node
     }
 }
 
-// Left and right derivatives D-V, D+V at node j of a line of n nodes from its stencil values,
-// both multiplied by dx.  Undivided first differences r[k] = u[k+1] - u[k] (WENO5: offsets
-// -2..3; upwind: 0..1).  On a
-// non-periodic dim a difference beyond an edge equals the nearest interior one (linear
-// extrapolation of V); waves whose nodes are all at least H nodes from both ends (inner, a
+// Undivided first differences along a line at node j from its stencil values u[0..2H]
+// (positions j-H..j+H): r[k] = u[k+1] - u[k] (WENO5: the differences entering at offsets -2..3;
+// upwind: 0..1).  On a non-periodic dim a difference beyond an edge equals the nearest interior
+// one (linear extrapolation of V), so the differences of a line form one extended sequence
+// that does not depend on the node: Delta_m = u(m) - u(m-1) for 1 <= m <= n-1, Delta_1 below,
+// Delta_{n-1} above.  Waves whose nodes are all at least H nodes from both ends (inner, a
 // per-wave vote, so the branch never diverges) skip that rule.
 template <typename T, int SPATIAL>
-__device__ __forceinline__ void line_derivs(const T *u, int j, int n, bool periodic, bool inner, T eps0, T &dm,
-                                            T &dp)
+__device__ __forceinline__ void line_diffs(const T *u, int j, int n, bool periodic, bool inner, T *r)
 {
     constexpr int H = SPATIAL == kWeno5 ? 3 : 1;
-    T r[2 * H];
 #pragma unroll
     for (int o = -H + 1; o <= H; ++o) r[o + H - 1] = u[o + H] - u[o + H - 1];
     if constexpr (SPATIAL == kUpwind1) {
@@ -352,6 +375,17 @@ __device__ __forceinline__ void line_derivs(const T *u, int j, int n, bool perio
             r[o + H - 1] = v;
         }
     }
+}
+
+// Left and right derivatives D-V, D+V at node j of a line of n nodes from its stencil values,
+// both multiplied by dx.
+template <typename T, int SPATIAL>
+__device__ __forceinline__ void line_derivs(const T *u, int j, int n, bool periodic, bool inner, T eps0, T &dm,
+                                            T &dp)
+{
+    constexpr int H = SPATIAL == kWeno5 ? 3 : 1;
+    T r[2 * H];
+    line_diffs<T, SPATIAL>(u, j, n, periodic, inner, r);
     if constexpr (SPATIAL == kWeno5) {
         weno5_pair<T>(r, eps0, dm, dp);
     } else {

@@ -490,6 +490,210 @@ __global__ __launch_bounds__(kBlock) void march_kernel(const Inst *__restrict__ 
 }
 
 // --------------------------------------------------------------------------------------------
+// Plane-march stage kernel for WENO5 stencils
+//
+// As march_tile: one thread per column, walking a run of dim-0 planes.  Along dim 0 the thread
+// keeps the column's six edge-extended differences around the current plane in registers and
+// computes each WENO5 interface once: the interface between planes i and i+1 gives D+ at i and
+// D- at i+1, so per node the dim-0 stencil costs one interface and two candidate combinations
+// where the flat kernel computes two interfaces, and one new load where the flat kernel makes
+// six.  Within the plane each dim takes its six neighbours at offsets fixed per column
+// (periodic ends wrapped, positions off the line replaced by the centre, as line_load does) and
+// the flat kernel's line_derivs.  The per-node arithmetic is that of stage_tile, so the results
+// are bitwise the same.
+// --------------------------------------------------------------------------------------------
+template <typename T, int DYN>
+__device__ __forceinline__ void march_tile_w5(const Inst &I, const MTile &tl, int stage, T dt, double *red)
+{
+    constexpr int N = DynDim<DYN>::value;
+    using F = Fields<T>;
+    SolveState *st = I.state;
+    const bool euler = I.temporal == kEuler;
+    const int par = euler ? st->parity : 0;
+    T *V = F::V(I), *A = F::A(I), *B = F::B(I);
+    const T *S, *Vn;
+    T *O;
+    if (euler) {
+        S = par ? A : V;
+        Vn = S;
+        O = par ? V : A;
+    } else if (stage == 0) {
+        S = V; Vn = V; O = A;
+    } else if (stage == 1) {
+        S = A; Vn = V; O = B;
+    } else {
+        S = B; Vn = V; O = V;
+    }
+    const bool last = euler || stage == 2;
+    const T *G = uniform_ptr(F::g(I));
+    const size_t fbytes = (size_t)I.npts * sizeof(T);
+    const __amdgpu_buffer_rsrc_t rS = buf(uniform_ptr(S), fbytes), rVn = buf(uniform_ptr(Vn), fbytes);
+    const __amdgpu_buffer_rsrc_t rO = buf(uniform_ptr(O), fbytes), rl = buf(uniform_ptr(F::l(I)), fbytes);
+    const __amdgpu_buffer_rsrc_t rG = buf(G, fbytes);
+    const T gm = (T)st->gamma;
+    const uint32_t P = I.stride[0];
+    const uint32_t pb = P * (uint32_t)sizeof(T);
+    const int n0 = I.n[0];
+    const bool per0 = I.periodic & 1u;
+    const uint32_t c = tl.c0 + threadIdx.x;
+    T delta = T(0);
+    if (threadIdx.x < tl.cn) {
+        int idx[N];
+        idx[0] = 0;
+        uint32_t rem = c;
+#pragma unroll
+        for (int d = N - 1; d >= 2; --d) {
+            const uint32_t q = fdiv(rem, I.div[d]);
+            idx[d] = (int)(rem - q * (uint32_t)I.n[d]);
+            rem = q;
+        }
+        if (N >= 2) idx[1] = (int)rem;
+        // byte offsets of the neighbours at -3, -2, -1, +1, +2, +3 along each dim of the plane
+        uint32_t off[N][6];
+        bool inner[N];
+#pragma unroll
+        for (int d = 1; d < N; ++d) {
+            const int j = idx[d], n = I.n[d];
+            const bool per = (I.periodic >> d) & 1u;
+            const int s = d == N - 1 ? 1 : (int)I.stride[d];
+            inner[d] = __all(j >= 3 && j < n - 3);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const int o = k < 3 ? k - 3 : k - 2;
+                int q;
+                if (per)
+                    q = o < 0 ? (j + o < 0 ? o + n : o) : (j + o >= n ? o - n : o);
+                else
+                    q = (o < 0 ? j + o >= 0 : j + o < n) ? o : 0;
+                off[d][k] = (uint32_t)((int)c + q * s) * (uint32_t)sizeof(T);
+            }
+        }
+        const HamCoef<T> kc = ham_coef<T, DYN>(I, uniform_ptr(F::tab(I)), idx);
+        const T sgn = I.game == 0 ? T(1) : T(-1);
+        const uint32_t cb = c * (uint32_t)sizeof(T);
+        const int i0 = tl.i0, i1 = tl.i0 + tl.len;
+        const bool proj = last && !I.brs;
+        const bool useg = last && G != nullptr;
+        const T eps00 = F::eps0(I, 0);
+        // planes i0-3 .. i0+3 (wrapped on a periodic dim 0; off the line the centre stands in)
+        // and the differences Delta_{i0-2} .. Delta_{i0+3} of the extended sequence
+        T D[6];
+        T u0, u1, u2, u3;  // S at planes i, i+1, i+2, i+3
+        {
+            T w[7];
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                int q = i0 + k - 3;
+                if (per0)
+                    q = q < 0 ? q + n0 : (q >= n0 ? q - n0 : q);
+                else
+                    q = (q < 0 || q >= n0) ? i0 : q;
+                w[k] = bld<T>(rS, cb, (uint32_t)q * pb);
+            }
+            line_diffs<T, kWeno5>(w, i0, n0, per0, false, D);
+            u0 = w[3];
+            u1 = w[4];
+            u2 = w[5];
+            u3 = w[6];
+        }
+        // D- at the current plane, from the interface on its left
+        T dmn;
+        {
+            const WenoIf<T> wl = weno5_interface(D[0], D[1], D[2], D[3], D[4], eps00);
+            dmn = weno5_left(wl, D[0], D[1], D[2], D[3], D[4]);
+        }
+        uint32_t so = (uint32_t)i0 * pb;
+        for (int i = i0; i < i1; ++i, so += pb) {
+            struct {
+                T u4, un[N][6], lv, gv, vn;
+            } cur;
+            {
+                // plane i+4 (its difference enters at the next plane); past a non-periodic end,
+                // or after the last plane of the run, plane i is read instead and not used
+                int q4 = i + 4;
+                if (per0) q4 = q4 >= n0 ? q4 - n0 : q4;
+                const bool need4 = i + 1 < i1 && (per0 || q4 < n0);
+                cur.u4 = bld<T>(rS, cb, need4 ? (uint32_t)q4 * pb : so);
+#pragma unroll
+                for (int d = 1; d < N; ++d)
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) cur.un[d][k] = bld<T>(rS, off[d][k], so);
+                cur.lv = proj ? bld<T>(rl, cb, so) : T(0);
+                cur.gv = useg ? bld<T>(rG, cb, so) : T(0);
+                cur.vn = euler ? T(0) : bld<T>(rVn, cb, so);
+            }
+            T p[N], diff[N], alpha[N];
+            {
+                const WenoIf<T> wr = weno5_interface(D[1], D[2], D[3], D[4], D[5], eps00);
+                const T dm = dmn;
+                const T dq = weno5_right(wr, D[1], D[2], D[3], D[4], D[5]);
+                dmn = weno5_left(wr, D[1], D[2], D[3], D[4], D[5]);
+                const T h = F::hinv_dx(I, 0);
+                p[0] = h * (dm + dq);
+                diff[0] = h * (dq - dm);
+            }
+#pragma unroll
+            for (int d = 1; d < N; ++d) {
+                const T uu[7] = {cur.un[d][0], cur.un[d][1], cur.un[d][2], u0,
+                                 cur.un[d][3], cur.un[d][4], cur.un[d][5]};
+                T dm, dq;
+                line_derivs<T, kWeno5>(uu, idx[d], I.n[d], (I.periodic >> d) & 1u, inner[d], F::eps0(I, d), dm, dq);
+                const T h = F::hinv_dx(I, d);
+                p[d] = h * (dm + dq);
+                diff[d] = h * (dq - dm);
+            }
+            T L = ham_eval<T, DYN>(I, kc, p, alpha, sgn);
+#pragma unroll
+            for (int d = 0; d < N; ++d) L += alpha[d] * diff[d];
+            const T s = u0;
+            const T vn = euler ? u0 : cur.vn;
+            T out;
+            if (euler) {
+                out = gm * (s + dt * L);
+                if (!I.brs) out = fmin(cur.lv, out);
+                if (G) out = fmax(cur.gv, out);
+            } else if (stage == 0) {
+                out = s + dt * L;
+            } else if (stage == 1) {
+                out = T(0.75) * vn + T(0.25) * (s + dt * L);
+            } else {
+                out = gm * (vn * T(1.0 / 3.0) + T(2.0 / 3.0) * (s + dt * L));
+                if (!I.brs) out = fmin(cur.lv, out);
+                if (G) out = fmax(cur.gv, out);
+            }
+            bst(rO, cb, so, out);
+            if (last) delta = nanmax(delta, T(fabs(out - vn)));
+            // slide: the difference Delta_{i+4} enters (past a non-periodic end it repeats the
+            // last interior one)
+            const T dnew = (per0 || i + 4 < n0) ? cur.u4 - u3 : D[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) D[k] = D[k + 1];
+            D[5] = dnew;
+            u0 = u1;
+            u1 = u2;
+            u2 = u3;
+            u3 = cur.u4;
+        }
+    }
+    if (last) block_max_to((double)delta, &st->delta_bits, red);
+}
+
+template <typename T, int DYN>
+__global__ __launch_bounds__(kBlock) void march_kernel_w5(const Inst *__restrict__ insts,
+                                                          const MTile *__restrict__ tiles, int ntiles, int stage)
+{
+    __shared__ double red[kBlock / 64];
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const MTile tl = tiles[t];
+    if (tl.cn == 0) return;  // padding
+    const Inst &I = insts[tl.inst];
+    const SolveState *st = I.state;
+    if (st->done != kRunning || stage >= I.nstages) return;
+    march_tile_w5<T, DYN>(I, tl, stage, (T)st->dt_cur, red);
+}
+
+// --------------------------------------------------------------------------------------------
 // Step bookkeeping (one thread per instance)
 // --------------------------------------------------------------------------------------------
 
@@ -864,16 +1068,22 @@ hipError_t launch_stage_one(bool fp64, int dyn, int spatial, int npt, const Inst
 }
 
 template <typename T>
-static void launch_march_t(int dyn, dim3 g, hipStream_t s, const Inst *insts, const MTile *tiles, int ntiles,
-                           int stage, hipEvent_t ev0, hipEvent_t ev1)
+static void launch_march_t(int dyn, int spatial, dim3 g, hipStream_t s, const Inst *insts, const MTile *tiles,
+                           int ntiles, int stage, hipEvent_t ev0, hipEvent_t ev1)
 {
-#define HJR_MARCH(D)                                                                                           \
+#define HJR_MARCH_K(K)                                                                                         \
     do {                                                                                                       \
         if (ev0 || ev1)                                                                                        \
-            hipExtLaunchKernelGGL((march_kernel<T, D>), g, dim3(kBlock), 0, s, ev0, ev1, 0u, insts, tiles, ntiles, \
-                                  stage);                                                                      \
+            hipExtLaunchKernelGGL((K), g, dim3(kBlock), 0, s, ev0, ev1, 0u, insts, tiles, ntiles, stage);      \
         else                                                                                                   \
-            hipLaunchKernelGGL((march_kernel<T, D>), g, dim3(kBlock), 0, s, insts, tiles, ntiles, stage);      \
+            hipLaunchKernelGGL((K), g, dim3(kBlock), 0, s, insts, tiles, ntiles, stage);                       \
+    } while (0)
+#define HJR_MARCH(D)                                                                                           \
+    do {                                                                                                       \
+        if (spatial == kWeno5)                                                                                 \
+            HJR_MARCH_K((march_kernel_w5<T, D>));                                                              \
+        else                                                                                                   \
+            HJR_MARCH_K((march_kernel<T, D>));                                                                 \
     } while (0)
     switch (dyn) {
     case kDynDI: HJR_MARCH(kDynDI); break;
@@ -885,6 +1095,7 @@ static void launch_march_t(int dyn, dim3 g, hipStream_t s, const Inst *insts, co
     default: break;
     }
 #undef HJR_MARCH
+#undef HJR_MARCH_K
 }
 
 void march_tiles(int inst, int ndim, const int *n, int len, std::vector<MTile> &out)
@@ -949,15 +1160,15 @@ void march_tiles(int inst, int ndim, const int *n, int len, std::vector<MTile> &
     for (size_t r = nb8; r < blocks.size(); ++r) out.insert(out.end(), blocks[r].begin(), blocks[r].end());
 }
 
-hipError_t launch_march(bool fp64, int dyn, const Inst *insts, const MTile *tiles, int ntiles, int stage,
-                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+hipError_t launch_march(bool fp64, int dyn, int spatial, const Inst *insts, const MTile *tiles, int ntiles,
+                        int stage, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (ntiles <= 0) return hipSuccess;
     const dim3 g(ntiles);
     if (fp64)
-        launch_march_t<double>(dyn, g, s, insts, tiles, ntiles, stage, ev0, ev1);
+        launch_march_t<double>(dyn, spatial, g, s, insts, tiles, ntiles, stage, ev0, ev1);
     else
-        launch_march_t<float>(dyn, g, s, insts, tiles, ntiles, stage, ev0, ev1);
+        launch_march_t<float>(dyn, spatial, g, s, insts, tiles, ntiles, stage, ev0, ev1);
     return hipGetLastError();
 }
 

@@ -13,11 +13,12 @@ hipError_t launch_stage(bool fp64, const Inst *insts, const Tile *tiles, int nti
 hipError_t launch_stage_one(bool fp64, int dyn, int spatial, int npt, const Inst *insts, const Tile *tiles, int ntiles,
                             int stage, int max_blocks, hipStream_t s, hipEvent_t ev0 = nullptr,
                             hipEvent_t ev1 = nullptr, bool local = false);
-// First-order upwind stages by the plane-march kernel: one thread per column, advancing through
-// the dim-0 planes of its tile; one workgroup per tile in list order (see march_tiles for the
-// order).  Every field of the instances must be below 4 GiB.
-hipError_t launch_march(bool fp64, int dyn, const Inst *insts, const MTile *tiles, int ntiles, int stage,
-                        hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Stages by the plane-march kernels (first-order upwind, or WENO5 with each dim-0 interface
+// computed once): one thread per column, advancing through the dim-0 planes of its tile; one
+// workgroup per tile in list order (see march_tiles for the order).  Every field of the
+// instances must be below 4 GiB.
+hipError_t launch_march(bool fp64, int dyn, int spatial, const Inst *insts, const MTile *tiles, int ntiles,
+                        int stage, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // The march tiles of one instance (grid dims n[0..ndim), its index `inst`), in the order its
 // workgroups should run: columns are cut into tiles of at most kBlock consecutive columns within

@@ -49,10 +49,13 @@ class WarmStartServer:
     """Drive an hjr.Context with a request stream; keep solutions resident as warm starts."""
 
     def __init__(self, ctx: "hjr.Context", warm: bool = True, resident_per_kind: int = 8,
-                 only_dominating: bool = False):
+                 only_dominating: bool = False, keep_outputs: bool = True):
+        """keep_outputs=False drops each request's result array once it is done, unless it stays
+        resident as a warm start (for long streams of large grids)."""
         self.ctx = ctx
         self.warm = warm
         self.only_dominating = only_dominating
+        self.keep_outputs = keep_outputs
         self.resident_per_kind = resident_per_kind
         self.resident = {}     # kind -> list of (key, V tensor, last use)
 
@@ -80,15 +83,18 @@ class WarmStartServer:
             lst.sort(key=lambda c: c[2])
             lst.pop(0)
 
-    def run(self, requests, torch, device, poll_interval=2e-4):
-        """Submit each request at its arrival time; returns the requests with timings filled."""
+    def run(self, requests, torch, device, poll_interval=2e-4, max_in_flight=None):
+        """Submit each request at its arrival time (at most max_in_flight submitted and not yet
+        done; later arrivals wait, and their latency counts the wait); returns the requests with
+        timings filled."""
         pending = sorted(requests, key=lambda r: r.arrival)
         active = {}
         t0 = time.perf_counter()
         i = 0
         while i < len(pending) or active:
             now = time.perf_counter() - t0
-            while i < len(pending) and pending[i].arrival <= now:
+            while (i < len(pending) and pending[i].arrival <= now
+                   and (max_in_flight is None or len(active) < max_in_flight)):
                 r = pending[i]
                 k, key, exact = self.pick_warm_start(r)
                 r.warm_from = key
@@ -107,6 +113,8 @@ class WarmStartServer:
                 r.done = time.perf_counter() - t0
                 if r.status == hjr.OK:
                     self.keep(r)
+                if not self.keep_outputs:
+                    r.V = None
             time.sleep(poll_interval)
         return requests
 

@@ -57,7 +57,7 @@ def test_struct_layouts_match_header():
 
 
 def test_defaults_and_strings():
-    assert hjr.abi_version() == 4
+    assert hjr.abi_version() == 5
     o = hjr.options()
     assert (o.spatial, o.temporal, o.precision, o.cfl, o.tol) == (hjr.WENO5, hjr.TVDRK3, hjr.FP32_POLISH64, 0.5, 1e-6)
     lib = hjr.load()

@@ -11,6 +11,8 @@ the oracle's own prior solution as k on both sides, so no oracle input comes fro
     oracle's solution (the polish is exact when it starts above it).
   * 6-D quadrotor (the benchmark's problem) on 9^6, upwind + Euler: cold, and warm-started from
     the solution with disturbance 0.3 (the new problem has 0.5).
+  * 3-D Dubins car 101^3, upwind + Euler: a new obstacle appears and the solve is warm-started
+    from the solution before it, with and without local updates.
 """
 import numpy as np
 import pytest
@@ -117,3 +119,27 @@ def test_quad6_fp32_polish_converged(gpu, hjrlib, quad9, monkeypatch, warm, conf
     err, band, mism = _figures(f"quad6 9^6 {'warm' if warm else 'cold'} FP32+polish kernel {config} "
                                f"({r['iterations']}+{r['polish_iterations']} steps)", V, Vw if warm else Vc, p.l)
     assert err <= band and mism == 0
+
+
+def test_dubins101_new_obstacle_warm_start_converged(gpu, hjrlib, orc):
+    """The local-change scenario: on the 101^3 Dubins grid a second obstacle (a disk of radius
+    0.5 at (3, 3)) appears and the value function is warm-started from the one before (Prop. 1:
+    the target grows, so the warm start is exact).  Upwind + Euler (WENO5 has no steady state
+    with the off-centre obstacle).  The GPU's FP32 + polish solve, with and without local
+    updates, matches the oracle's converged solve from the same prior."""
+    p = W.dubins_problem(101, dbar=0.1, scheme="upwind")
+    l2 = np.minimum(p.l, W.disk_sdf(p.grid, (3.0, 3.0), 0.5))
+    opts = orc.problem_opts(p)
+    print("[converged] oracle 101^3 Dubins upwind solves (old obstacle, then the new one warm) ...", flush=True)
+    K, ik = orc.solve(p.grid, p.dyn, p.l, **opts)
+    Vo, io = orc.solve(p.grid, p.dyn, l2, K, **opts)
+    assert ik["converged"] == io["converged"] == 1
+    q = W.Problem(p.name, p.grid, p.dyn, l2, spatial=p.spatial, temporal=p.temporal, cfl=p.cfl, tol=p.tol)
+    for local in (0, 1):
+        opts_g = hjrlib.problem_options(q, precision=hjrlib.FP32_POLISH64, max_iter=20000, local_updates=local)
+        V, r, st = _gpu_solve(hjrlib, gpu, q, K, **opts_g)
+        assert st == hjrlib.OK
+        err, band, mism = _figures(f"dubins101 new obstacle warm, local_updates={local} "
+                                   f"({r['iterations']}+{r['polish_iterations']} steps; oracle {io['steps']})",
+                                   V, Vo, l2)
+        assert err <= band and mism == 0

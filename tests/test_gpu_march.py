@@ -1,12 +1,15 @@
-"""The plane-march stage kernel (first-order upwind; one thread per column walking the dim-0
-planes) against the flat-tile kernel and the FP64 oracle.
+"""The plane-march stage kernels (one thread per column walking the dim-0 planes; first-order
+upwind, and WENO5 with each dim-0 interface computed once) against the flat-tile kernel and the
+FP64 oracle.
 
-The march kernel evaluates the same per-node arithmetic as the flat-tile kernels, only with the
+The march kernels evaluate the same per-node arithmetic as the flat-tile kernels, only with the
 column's offsets, edge rule and model coordinates set up once per column and the dim-0
-neighbours carried in registers, so every output and every max-change reduction must be bitwise
-identical to the flat kernel's, for every model, game, precision, integrator stage, ragged grid
-and periodic dimension (dim 0 included).  The oracle then pins the common result (FP64: 1e-12,
-FP32: 2e-5 of the field's scale, as in the stage parity tests).
+neighbours (upwind) or dim-0 differences and interfaces (WENO5) carried in registers, so every
+output and every max-change reduction must be bitwise identical to the flat kernel's, for every
+scheme, model, game, precision, integrator stage, ragged grid, periodic dimension (dim 0
+included) and run length (whole lines, and runs of 8, 4 and 2 planes, whose ends fall at
+different distances from the grid's edges).  The oracle then pins the common result (FP64:
+1e-12, FP32: 2e-5 of the field's scale, as in the stage parity tests).
 """
 import math
 
@@ -37,12 +40,12 @@ def _cases():
     ]
 
 
-def _run_stage(hjrlib, monkeypatch, cfg, g, d, stage, dt, src, vn, l, temporal, prec, game):
+def _run_stage(hjrlib, monkeypatch, cfg, g, d, stage, dt, src, vn, l, temporal, prec, game, spatial):
     import torch
 
     monkeypatch.setenv("HJR_NPT", cfg)
     out = torch.empty_like(vn)
-    delta = hjrlib.stage_device(g, d, stage, dt, src, vn, l, out, game=game, spatial=hjrlib.UPWIND1,
+    delta = hjrlib.stage_device(g, d, stage, dt, src, vn, l, out, game=game, spatial=spatial,
                                 temporal=temporal, precision=prec)
     torch.cuda.synchronize()
     return out, delta
@@ -51,13 +54,14 @@ def _run_stage(hjrlib, monkeypatch, cfg, g, d, stage, dt, src, vn, l, temporal, 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("temporal", [1, 3], ids=["euler", "rk3"])
 @pytest.mark.parametrize("game", [0, 1], ids=["avoid", "reach"])
+@pytest.mark.parametrize("spatial", [1, 5], ids=["upwind", "weno5"])
 @pytest.mark.parametrize("case", _cases(), ids=lambda c: c[0])
-def test_march_stage_bitwise_equals_flat_and_matches_oracle(gpu, hjrlib, orc, monkeypatch, case, temporal,
+def test_march_stage_bitwise_equals_flat_and_matches_oracle(gpu, hjrlib, orc, monkeypatch, case, spatial, temporal,
                                                             precision, game):
     import torch
 
     name, g, d = case
-    print(f"[march] {name} {g.n} temporal={temporal} {precision} game={game}", flush=True)
+    print(f"[march] {name} {g.n} spatial={spatial} temporal={temporal} {precision} game={game}", flush=True)
     rng = np.random.default_rng(SEED)
     Vn = W.smooth_field(g, seed=SEED)
     Vs = Vn + 0.05 * W.smooth_field(g, seed=SEED + 1, kinks=False)
@@ -75,13 +79,15 @@ def test_march_stage_bitwise_equals_flat_and_matches_oracle(gpu, hjrlib, orc, mo
     tol = 2e-5 * scale if precision == "fp32" else 1e-12 * scale
     for stage in range(1, (3 if temporal == 3 else 1) + 1):
         src = t_vn if stage == 1 else t_vs
-        flat, dflat = _run_stage(hjrlib, monkeypatch, "4", g, d, stage, dt, src, t_vn, t_l, temporal, prec, game)
-        for cfg in ("-1", "-8"):
-            got, dgot = _run_stage(hjrlib, monkeypatch, cfg, g, d, stage, dt, src, t_vn, t_l, temporal, prec, game)
+        flat, dflat = _run_stage(hjrlib, monkeypatch, "4", g, d, stage, dt, src, t_vn, t_l, temporal, prec, game,
+                                 spatial)
+        for cfg in ("-1", "-8", "-4", "-2"):
+            got, dgot = _run_stage(hjrlib, monkeypatch, cfg, g, d, stage, dt, src, t_vn, t_l, temporal, prec, game,
+                                   spatial)
             assert torch.equal(got, flat), (name, stage, cfg, float((got.double() - flat.double()).abs().max()))
             assert (dgot is None and dflat is None) or dgot == dflat
-        ref = orc.stage_at(g, d, stage, dt, (Vn if stage == 1 else Vs), Vn, l, nodes, spatial=1, temporal=temporal,
-                           game=game)
+        ref = orc.stage_at(g, d, stage, dt, (Vn if stage == 1 else Vs), Vn, l, nodes, spatial=spatial,
+                           temporal=temporal, game=game)
         err = np.abs(flat.double().cpu().numpy().ravel()[nodes] - ref).max()
         assert err <= tol, (name, stage, err)
 
@@ -113,3 +119,26 @@ def test_march_solves_bitwise_equal_flat(gpu, hjrlib, monkeypatch):
         for warm in (False, True):
             a, b = results[("4", warm)], results[(cfg, warm)]
             assert a[:2] == b[:2] and torch.equal(a[2], b[2])
+
+
+def test_weno_march_solves_bitwise_equal_flat(gpu, hjrlib, monkeypatch):
+    """Whole WENO5 + TVD-RK3 FP32 + FP64-polish solves of the 101^3 Dubins car, cold: the march
+    configurations and the flat one give the same iterations and bitwise the same V."""
+    import torch
+
+    from paper_1903_07715_amd import hjr
+
+    p = W.dubins_problem(101)
+    lt = torch.tensor(p.l, device=gpu)
+    opts = hjr.problem_options(p, precision=hjrlib.FP32_POLISH64, max_iter=20000)
+    results = {}
+    for cfg in ("4", "-4", "-1"):
+        monkeypatch.setenv("HJR_NPT", cfg)
+        V = torch.empty_like(lt)
+        r, st = hjrlib.solve_device(p.grid, p.dyn, lt, None, V, **opts)
+        print(f"[march] WENO5 solve cfg={cfg}: {r['iterations']}+{r['polish_iterations']} status {st}", flush=True)
+        assert st == hjrlib.OK
+        results[cfg] = (r["iterations"], r["polish_iterations"], V.cpu())
+    for cfg in ("-4", "-1"):
+        a, b = results["4"], results[cfg]
+        assert a[:2] == b[:2] and torch.equal(a[2], b[2])
