@@ -153,6 +153,7 @@ typedef struct {
                                as many while the change is above 64 tol), the phase ends as
                                stalled.  A stalled FP32 phase hands over to the polish; a
                                stalled final phase returns HJR_NOT_CONVERGED with converged = 3.
+                               The polish waits 8 times as long (its stall is final).
                                0 = 128; < 0 disables.  HJR_FP64 solves never stop this way. */
     int32_t brs;            /* 0 (default): the backward reachable tube of the VI, eq. (7): every step
                                ends with V <- min(l, V).  1: the backward reachable set of Sec. II

@@ -296,10 +296,11 @@ struct Request {
     int64_t ticket = 0;
     double t_submit = 0.0, t_start = 0.0;
     bool done = false;
-    // march tiles of this request in its slot, for runs of mtiles_len planes (-1: none built);
-    // kept across engine rebuilds, which happen at every admission, hand-over and completion
+    // march tiles of this request in its slot for launch configuration mtiles_cfg (0: none
+    // built); kept across engine rebuilds, which happen at every admission, hand-over and
+    // completion
     std::vector<MTile> mtiles;
-    int mtiles_len = -1;
+    int mtiles_cfg = 0;
 };
 
 static void make_constants(const hjr_dynamics &dy, double c[8])
@@ -1209,7 +1210,7 @@ private:
                 const int off = (int)t[p].size();
                 if (!is_march(cfg) || any_interval_) append_tiles(kv.second.slots, is_march(cfg) ? 4 : cfg, t[p]);
                 const int moff = (int)mt[p].size();
-                if (is_march(cfg)) append_march_tiles(kv.second.slots, cfg == kMarchFull ? 0 : -cfg, mt[p]);
+                if (is_march(cfg)) append_march_tiles(kv.second.slots, cfg, mt[p]);
                 segs_[p].push_back(Seg{dyn, sp, cfg, off, (int)t[p].size() - off, moff, (int)mt[p].size() - moff,
                                        (int64_t)kv.second.nodes, tkey, local, kv.second.slots});
             }
@@ -1262,15 +1263,16 @@ private:
         }
     }
 
-    // March tiles of each instance, `len` dim-0 planes each (0: the whole line), in XCD order.
-    void append_march_tiles(const std::vector<int> &slots, int len, std::vector<MTile> &out)
+    // March tiles of each instance for configuration cfg (runs of -cfg dim-0 planes, kMarchFull
+    // the whole line), in XCD order.
+    void append_march_tiles(const std::vector<int> &slots, int cfg, std::vector<MTile> &out)
     {
         for (int i : slots) {
             Request *r = slots_[i];
-            if (r->mtiles_len != len) {
+            if (r->mtiles_cfg != cfg) {
                 r->mtiles.clear();
-                march_tiles(i, r->grid.ndim, r->grid.n, len, r->mtiles);
-                r->mtiles_len = len;
+                march_tiles(i, r->grid.ndim, r->grid.n, cfg == kMarchFull ? 0 : -cfg, r->mtiles);
+                r->mtiles_cfg = cfg;
             }
             out.insert(out.end(), r->mtiles.begin(), r->mtiles.end());
         }

@@ -235,8 +235,12 @@ template <typename T> struct WenoIf {
 // The WENO5 arithmetic below is written with explicit fused multiply-adds and contraction off,
 // so its rounding is fixed by the source alone: the flat kernel (both interfaces of every node)
 // and the march kernel (each interface once, shared by two nodes) produce the same bits.
+// m: the largest of e1^2 .. e5^2 (a maximum is exact, so any grouping gives the same value; the
+// flat kernel shares the middle four squares between a node's two interfaces).  The second
+// differences and their (13/3) c^2 terms are the same expressions in both interfaces of a node,
+// so the flat kernel computes the shared ones once.
 template <typename T>
-__device__ __forceinline__ WenoIf<T> weno5_interface(T e1, T e2, T e3, T e4, T e5, T eps0)
+__device__ __forceinline__ WenoIf<T> weno5_interface_m(T e1, T e2, T e3, T e4, T e5, T m, T eps0)
 {
 #pragma clang fp contract(off)
     const T k = T(13.0 / 3.0);
@@ -246,16 +250,23 @@ __device__ __forceinline__ WenoIf<T> weno5_interface(T e1, T e2, T e3, T e4, T e
     const T rA = fma(T(3), e3, fma(T(-4), e2, e1));
     const T rB = e2 - e4;
     const T rC = fma(T(3), e3, fma(T(-4), e4, e5));
-    const T SA = fma(k * cA, cA, rA * rA);
-    const T SB = fma(k * cB, cB, rB * rB);
-    const T SC = fma(k * cC, cC, rC * rC);
-    const T m = fmax(fmax(fmax(e2 * e2, e3 * e3), e4 * e4), fmax(e1 * e1, e5 * e5));
+    const T SA = fma(rA, rA, (k * cA) * cA);
+    const T SB = fma(rB, rB, (k * cB) * cB);
+    const T SC = fma(rC, rC, (k * cC) * cC);
     const T eps = fma(T(4e-6), m, eps0);
     const T sc = pow2_recip(eps);
     const T e = eps * sc;
     const T tA = fma(SA, sc, e), tB = fma(SB, sc, e), tC = fma(SC, sc, e);
     const T sA = tA * tA, sB = tB * tB, sC = tC * tC;
     return WenoIf<T>{sA * sB, sA * sC, sB * sC};
+}
+
+template <typename T>
+__device__ __forceinline__ WenoIf<T> weno5_interface(T e1, T e2, T e3, T e4, T e5, T eps0)
+{
+#pragma clang fp contract(off)
+    const T m = fmax(fmax(fmax(e2 * e2, e3 * e3), e4 * e4), fmax(e1 * e1, e5 * e5));
+    return weno5_interface_m(e1, e2, e3, e4, e5, m, eps0);
 }
 
 // D- at the node right of the interface: v = (e1..e5), weights 1 : 6 : 3 on A, B, C.
@@ -289,8 +300,10 @@ __device__ __forceinline__ T weno5_right(const WenoIf<T> &w, T e1, T e2, T e3, T
 template <typename T>
 __device__ __forceinline__ void weno5_pair(const T *d, T eps0, T &dm, T &dp)
 {
-    const WenoIf<T> wl = weno5_interface(d[0], d[1], d[2], d[3], d[4], eps0);
-    const WenoIf<T> wr = weno5_interface(d[1], d[2], d[3], d[4], d[5], eps0);
+#pragma clang fp contract(off)
+    const T mid = fmax(fmax(d[1] * d[1], d[2] * d[2]), fmax(d[3] * d[3], d[4] * d[4]));
+    const WenoIf<T> wl = weno5_interface_m(d[0], d[1], d[2], d[3], d[4], fmax(mid, d[0] * d[0]), eps0);
+    const WenoIf<T> wr = weno5_interface_m(d[1], d[2], d[3], d[4], d[5], fmax(mid, d[5] * d[5]), eps0);
     dm = weno5_left(wl, d[0], d[1], d[2], d[3], d[4]);
     dp = weno5_right(wr, d[1], d[2], d[3], d[4], d[5]);
 }

@@ -319,13 +319,16 @@ __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, uint
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, soff, 0);
 }
 
-template <typename T, int DYN>
+// EP: the instance takes forward Euler steps projected on l with no constraint function (the
+// common case), so every node makes the same loads; the compiler can then keep the next plane's
+// loads in flight across this plane's arithmetic (a load under a branch makes it wait for all).
+template <typename T, int DYN, bool EP>
 __device__ __forceinline__ void march_tile(const Inst &I, const MTile &tl, int stage, T dt, double *red)
 {
     constexpr int N = DynDim<DYN>::value;
     using F = Fields<T>;
     SolveState *st = I.state;
-    const bool euler = I.temporal == kEuler;
+    const bool euler = EP || I.temporal == kEuler;
     const int par = euler ? st->parity : 0;
     T *V = F::V(I), *A = F::A(I), *B = F::B(I);
     const T *S, *Vn;
@@ -342,7 +345,7 @@ __device__ __forceinline__ void march_tile(const Inst &I, const MTile &tl, int s
         S = B; Vn = V; O = V;
     }
     const bool last = euler || stage == 2;
-    const T *G = uniform_ptr(F::g(I));  // reach-avoid constraint, or nullptr
+    const T *G = EP ? nullptr : uniform_ptr(F::g(I));  // reach-avoid constraint, or nullptr
     const size_t fbytes = (size_t)I.npts * sizeof(T);
     const __amdgpu_buffer_rsrc_t rS = buf(uniform_ptr(S), fbytes), rVn = buf(uniform_ptr(Vn), fbytes);
     const __amdgpu_buffer_rsrc_t rO = buf(uniform_ptr(O), fbytes), rl = buf(uniform_ptr(F::l(I)), fbytes);
@@ -396,33 +399,37 @@ __device__ __forceinline__ void march_tile(const Inst &I, const MTile &tl, int s
         const T sgn = I.game == 0 ? T(1) : T(-1);
         const uint32_t cb = c * (uint32_t)sizeof(T);
         const int i0 = tl.i0, i1 = tl.i0 + tl.len;
-        const bool proj = last && !I.brs;
-        const bool useg = last && G != nullptr;
+        const bool proj = EP || (last && !I.brs);
+        const bool useg = !EP && last && G != nullptr;
         // values of S at planes i - 1 and i; at a non-periodic end the centre stands in for the
         // missing neighbour (its difference is replaced below)
         const int im = i0 > 0 ? i0 - 1 : (per0 ? n0 - 1 : 0);
         T um = bld<T>(rS, cb, (uint32_t)im * pb);
         T u0 = bld<T>(rS, cb, (uint32_t)i0 * pb);
-        uint32_t so = (uint32_t)i0 * pb;  // byte offset of plane i
-        for (int i = i0; i < i1; ++i, so += pb) {
-            // every load of the node first (the next plane's value, the neighbours within the
-            // plane, l, the constraint, the step-start value), so they are in flight together
-            struct {
-                T up, un[N], unp[N], lv, gv, vn;
-            } cur;
-            {
-                const uint32_t sp1 = i + 1 < n0 ? so + pb : (per0 ? 0u : so);
-                cur.up = bld<T>(rS, cb, sp1);
+        // every load a node needs (the next plane's value, the neighbours within the plane, l,
+        // the constraint, the step-start value), issued together
+        struct Cur {
+            T up, un[N], unp[N], lv, gv, vn;
+        };
+        auto load_plane = [&](int i, uint32_t so) {
+            Cur c;
+            const uint32_t sp1 = i + 1 < n0 ? so + pb : (per0 ? 0u : so);
+            c.up = bld<T>(rS, cb, sp1);
 #pragma unroll
-                for (int d = 1; d < N; ++d) {
-                    cur.un[d] = bld<T>(rS, om[d], so);
-                    cur.unp[d] = bld<T>(rS, op[d], so);
-                }
-                cur.lv = proj ? bld<T>(rl, cb, so) : T(0);
-                cur.gv = useg ? bld<T>(rG, cb, so) : T(0);
-                cur.vn = euler ? T(0) : bld<T>(rVn, cb, so);
+            for (int d = 1; d < N; ++d) {
+                c.un[d] = bld<T>(rS, om[d], so);
+                c.unp[d] = bld<T>(rS, op[d], so);
             }
-            const T up = cur.up;
+            c.lv = proj ? bld<T>(rl, cb, so) : T(0);
+            c.gv = useg ? bld<T>(rG, cb, so) : T(0);
+            c.vn = euler ? T(0) : bld<T>(rVn, cb, so);
+            return c;
+        };
+        // the node at plane i from its loads c (so is the same in every lane; saying so keeps the
+        // store's offset in a scalar register)
+        auto node = [&](int i, uint32_t so, const Cur &c) {
+            so = __builtin_amdgcn_readfirstlane(so);
+            const T up = c.up;
             T p[N], diff[N], alpha[N];
             {
                 T dm = u0 - um, dq = up - u0;
@@ -437,8 +444,8 @@ __device__ __forceinline__ void march_tile(const Inst &I, const MTile &tl, int s
             }
 #pragma unroll
             for (int d = 1; d < N; ++d) {
-                const T dm = sm[d] * (u0 - cur.un[d]);
-                const T dq = sp[d] * (cur.unp[d] - u0);
+                const T dm = sm[d] * (u0 - c.un[d]);
+                const T dq = sp[d] * (c.unp[d] - u0);
                 const T h = F::hinv_dx(I, d);
                 p[d] = h * (dm + dq);
                 diff[d] = h * (dq - dm);
@@ -447,25 +454,45 @@ __device__ __forceinline__ void march_tile(const Inst &I, const MTile &tl, int s
 #pragma unroll
             for (int d = 0; d < N; ++d) L += alpha[d] * diff[d];
             const T s = u0;
-            const T vn = euler ? u0 : cur.vn;
+            const T vn = euler ? u0 : c.vn;
             T out;
-            if (euler) {
+            if (EP) {
+                out = fmin(c.lv, gm * (s + dt * L));
+            } else if (euler) {
                 out = gm * (s + dt * L);
-                if (!I.brs) out = fmin(cur.lv, out);
-                if (G) out = fmax(cur.gv, out);
+                if (!I.brs) out = fmin(c.lv, out);
+                if (G) out = fmax(c.gv, out);
             } else if (stage == 0) {
                 out = s + dt * L;
             } else if (stage == 1) {
                 out = T(0.75) * vn + T(0.25) * (s + dt * L);
             } else {
                 out = gm * (vn * T(1.0 / 3.0) + T(2.0 / 3.0) * (s + dt * L));
-                if (!I.brs) out = fmin(cur.lv, out);
-                if (G) out = fmax(cur.gv, out);
+                if (!I.brs) out = fmin(c.lv, out);
+                if (G) out = fmax(c.gv, out);
             }
             bst(rO, cb, so, out);
             if (last) delta = nanmax(delta, T(fabs(out - vn)));
             um = u0;
             u0 = up;
+        };
+        // Two planes per trip, with two sets of load registers used in turn: the next plane's
+        // loads go out before this plane's arithmetic, so the loads of two planes are in flight
+        // at once, and no register copy waits for a load (the last plane of a run reloads
+        // itself, unused).
+        uint32_t so = (uint32_t)i0 * pb;  // byte offset of plane i
+        Cur ca = load_plane(i0, so);
+        // (the scheduling barriers keep the compiler from moving the loads after the arithmetic)
+        for (int i = i0; i < i1; i += 2, so += 2 * pb) {
+            const int ib = i + 1 < i1 ? i + 1 : i;
+            const Cur cn = load_plane(ib, (uint32_t)ib * pb);
+            asm volatile("" ::: "memory");
+            node(i, so, ca);
+            if (i + 1 >= i1) break;
+            const int ia = i + 2 < i1 ? i + 2 : i + 1;
+            ca = load_plane(ia, (uint32_t)ia * pb);
+            asm volatile("" ::: "memory");
+            node(i + 1, so + pb, cn);
         }
     }
     if (last) block_max_to((double)delta, &st->delta_bits, red);
@@ -486,7 +513,10 @@ __global__ __launch_bounds__(kBlock) void march_kernel(const Inst *__restrict__ 
     const Inst &I = insts[tl.inst];
     const SolveState *st = I.state;
     if (st->done != kRunning || stage >= I.nstages) return;
-    march_tile<T, DYN>(I, tl, stage, (T)st->dt_cur, red);
+    if (I.temporal == kEuler && !I.brs && Fields<T>::g(I) == nullptr)
+        march_tile<T, DYN, true>(I, tl, stage, (T)st->dt_cur, red);
+    else
+        march_tile<T, DYN, false>(I, tl, stage, (T)st->dt_cur, red);
 }
 
 // --------------------------------------------------------------------------------------------
@@ -949,6 +979,9 @@ __global__ void polish_switch_kernel(const Inst *__restrict__ insts, int inst, d
     st->tol = st->tol_final;
     st->best_delta = INFINITY;  // stall detection restarts for the polish
     st->n_best = 0;
+    // a stalled polish ends the solve unconverged, so it waits 8 times as long as the FP32 phase
+    // (slow tails, where the change creeps towards the threshold, are not stalls)
+    if (st->stall_window > 0) st->stall_window = st->stall_window < (1ll << 40) ? 8 * st->stall_window : st->stall_window;
     st->dt_cur = next_dt(st);
 }
 

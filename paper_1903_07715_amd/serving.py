@@ -83,14 +83,15 @@ class WarmStartServer:
             lst.sort(key=lambda c: c[2])
             lst.pop(0)
 
-    def run(self, requests, torch, device, poll_interval=2e-4, max_in_flight=None):
+    def run(self, requests, torch, device, poll_interval=2e-4, max_in_flight=None, on_done=None):
         """Submit each request at its arrival time (at most max_in_flight submitted and not yet
         done; later arrivals wait, and their latency counts the wait); returns the requests with
-        timings filled."""
+        timings filled.  on_done(request, finished_count) is called as each request finishes."""
         pending = sorted(requests, key=lambda r: r.arrival)
         active = {}
         t0 = time.perf_counter()
         i = 0
+        finished = 0
         while i < len(pending) or active:
             now = time.perf_counter() - t0
             while (i < len(pending) and pending[i].arrival <= now
@@ -115,6 +116,9 @@ class WarmStartServer:
                     self.keep(r)
                 if not self.keep_outputs:
                     r.V = None
+                finished += 1
+                if on_done is not None:
+                    on_done(r, finished)
             time.sleep(poll_interval)
         return requests
 

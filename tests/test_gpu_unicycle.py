@@ -6,12 +6,19 @@ near 3e-3 after 1500 steps on 31^4), so its parity is checked over fixed numbers
   * all 13.8 M nodes of the 61^4 grid after 10 steps, cold and warm-started (k = the oracle's
     10-step result for the obstacles before the move), FP64 and FP32;
   * the finite-horizon tube at T = 2 on 31^4, cold and warm-started from the tube before the
-    move, FP64 and FP32.
+    move, FP64 and FP32.  A horizon solve ends without a polish, so its FP32 result carries the
+    FP32 rounding of every stage, which the 1e-4 max|l| target (stated for FP32 + polish
+    results) does not cover.  Its bar comes from the arithmetic: the oracle's own change when
+    its inputs (l, and k) are rounded to FP32, i.e. the problem's response to one FP32 rounding
+    of V, times the square root of the number of roundings (one per RK stage), or 1e-4 max|l|
+    if that is larger.
 Theorem 1 (the warm start is conservative) holds exactly only for a monotone scheme without
 boundary effects, which the oracle's pins check; on this bounded grid the oracle's own warm and
 cold tubes violate it at a few nodes near the edges (by at most 0.05 with WENO5, 0.025 with the
 upwind scheme), so it is not asserted here.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -69,13 +76,19 @@ def uni31_tube(orc):
     Vc, ic = orc.solve(new.grid, new.dyn, new.l, **opts)
     Vw, iw = orc.solve(new.grid, new.dyn, new.l, K, **opts)
     assert ic["converged"] == iw["converged"] == 2
-    return new, K, Vc, Vw
+    # the same tubes from inputs rounded to FP32: the problem's response to one FP32 rounding
+    r32 = lambda a: a.astype(np.float32).astype(np.float64)
+    Vc32, _ = orc.solve(new.grid, new.dyn, r32(new.l), **opts)
+    Vw32, _ = orc.solve(new.grid, new.dyn, r32(new.l), r32(K), **opts)
+    sens = {False: (float(np.abs(Vc - Vc32).max()), ic["steps"]), True: (float(np.abs(Vw - Vw32).max()), iw["steps"])}
+    print(f"[unicycle] FP32 input sensitivity: cold {sens[False][0]:.3e}, warm {sens[True][0]:.3e}", flush=True)
+    return new, K, Vc, Vw, sens
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("warm", [False, True], ids=["cold", "warm"])
 def test_unicycle31_tube_to_horizon(gpu, hjrlib, uni31_tube, warm, precision):
-    new, K, Vc, Vw = uni31_tube
+    new, K, Vc, Vw, sens = uni31_tube
     prec = hjrlib.FP64 if precision == "fp64" else hjrlib.FP32
     opts = hjrlib.problem_options(new, precision=prec, t_max=2.0, tol=1e-300, max_iter=100000, stall_window=-1)
     V, r, st = _gpu(hjrlib, gpu, new, K if warm else None, **opts)
@@ -86,5 +99,10 @@ def test_unicycle31_tube_to_horizon(gpu, hjrlib, uni31_tube, warm, precision):
     mism = int(np.sum(((V <= 0) != (Vo <= 0)) & (np.abs(Vo) > band)))
     print(f"[unicycle] 31^4 tube T=2 {'warm' if warm else 'cold'} {precision}: max|V - V_oracle| {err:.3e} "
           f"(bar {band:.3e}), off-band sign mismatches {mism}", flush=True)
-    bar = 1e-9 * float(np.abs(new.l).max()) if precision == "fp64" else band
+    if precision == "fp64":
+        bar = 1e-9 * float(np.abs(new.l).max())
+    else:
+        delta, steps = sens[warm]
+        bar = max(band, math.sqrt(3 * steps) * delta)
+    print(f"[unicycle]   bar {bar:.3e} ({err / bar:.3f} of it)", flush=True)
     assert err <= bar and mism == 0
