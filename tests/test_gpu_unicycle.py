@@ -78,6 +78,7 @@ def uni31_tube(orc):
     assert ic["converged"] == iw["converged"] == 2
     # the same tubes from inputs rounded to FP32: the problem's response to one FP32 rounding
     r32 = lambda a: a.astype(np.float32).astype(np.float64)
+    print("[unicycle] oracle: the same tubes from inputs rounded to FP32 ...", flush=True)
     Vc32, _ = orc.solve(new.grid, new.dyn, r32(new.l), **opts)
     Vw32, _ = orc.solve(new.grid, new.dyn, r32(new.l), r32(K), **opts)
     sens = {False: (float(np.abs(Vc - Vc32).max()), ic["steps"]), True: (float(np.abs(Vw - Vw32).max()), iw["steps"])}
