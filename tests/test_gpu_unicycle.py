@@ -11,7 +11,10 @@ near 3e-3 after 1500 steps on 31^4), so its parity is checked over fixed numbers
     results) does not cover.  Its bar comes from the arithmetic: the oracle's own change when
     its inputs (l, and k) are rounded to FP32, i.e. the problem's response to one FP32 rounding
     of V, times the square root of the number of roundings (one per RK stage), or 1e-4 max|l|
-    if that is larger.
+    if that is larger;
+  * converged FP32 + polish solves on 31^4 with the benchmark's monotone scheme (upwind +
+    Euler), cold and warm-started from the converged solution before the move, flat and march
+    kernels.
 Theorem 1 (the warm start is conservative) holds exactly only for a monotone scheme without
 boundary effects, which the oracle's pins check; on this bounded grid the oracle's own warm and
 cold tubes violate it at a few nodes near the edges (by at most 0.05 with WENO5, 0.025 with the
@@ -107,3 +110,43 @@ def test_unicycle31_tube_to_horizon(gpu, hjrlib, uni31_tube, warm, precision):
         bar = max(band, math.sqrt(3 * steps) * delta)
     print(f"[unicycle]   bar {bar:.3e} ({err / bar:.3f} of it)", flush=True)
     assert err <= bar and mism == 0
+
+
+@pytest.fixture(scope="module")
+def uni31_converged(orc):
+    """The benchmark's unicycle scheme (upwind + Euler, CFL 0.8), which converges, on 31^4: the
+    converged value function before the move, and after it cold and warm-started from the one
+    before (Theorem 1's conservative case)."""
+    old = W.unicycle_problem(31)
+    new = W.unicycle_problem(31, moved=True)
+    for p in (old, new):
+        p.spatial, p.temporal, p.cfl = 1, 1, 0.8
+    opts = orc.problem_opts(new)
+    print("[unicycle] oracle: converged 31^4 upwind solves (before the move, then cold and warm) ...", flush=True)
+    K, ik = orc.solve(old.grid, old.dyn, old.l, **opts)
+    print(f"[unicycle]   before the move: {ik['steps']} steps", flush=True)
+    Vc, ic = orc.solve(new.grid, new.dyn, new.l, **opts)
+    Vw, iw = orc.solve(new.grid, new.dyn, new.l, K, **opts)
+    print(f"[unicycle]   after: cold {ic['steps']} steps, warm {iw['steps']}", flush=True)
+    assert ik["converged"] == ic["converged"] == iw["converged"] == 1
+    return new, K, Vc, Vw
+
+
+@pytest.mark.parametrize("config", ["4", "-1"], ids=["flat", "march"])
+@pytest.mark.parametrize("warm", [False, True], ids=["cold", "warm"])
+def test_unicycle31_fp32_polish_converged(gpu, hjrlib, uni31_converged, monkeypatch, warm, config):
+    """Converged FP32 + FP64-polish solves of the moved-obstacle unicycle against the oracle's,
+    from the same start: within 1e-4 max|l| and no sign mismatch off that band."""
+    new, K, Vc, Vw = uni31_converged
+    monkeypatch.setenv("HJR_NPT", config)
+    opts = hjrlib.problem_options(new, precision=hjrlib.FP32_POLISH64, max_iter=20000)
+    V, r, st = _gpu(hjrlib, gpu, new, K if warm else None, **opts)
+    assert st == hjrlib.OK
+    Vo = Vw if warm else Vc
+    band = 1e-4 * float(np.abs(new.l).max())
+    err = float(np.abs(V - Vo).max())
+    mism = int(np.sum(((V <= 0) != (Vo <= 0)) & (np.abs(Vo) > band)))
+    print(f"[unicycle] 31^4 converged {'warm' if warm else 'cold'} kernel {config} "
+          f"({r['iterations']}+{r['polish_iterations']} steps): max|V - V_oracle| {err:.3e} (bar {band:.3e}), "
+          f"off-band sign mismatches {mism}", flush=True)
+    assert err <= band and mism == 0
