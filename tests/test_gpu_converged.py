@@ -13,6 +13,7 @@ the oracle's own prior solution as k on both sides, so no oracle input comes fro
     the solution with disturbance 0.3 (the new problem has 0.5).
   * 3-D Dubins car 101^3, upwind + Euler: a new obstacle appears and the solve is warm-started
     from the solution before it, with and without local updates.
+  * the 6-D quadrotor on 13^6, cold, with the plane-march kernel.
 """
 import numpy as np
 import pytest
@@ -143,3 +144,20 @@ def test_dubins101_new_obstacle_warm_start_converged(gpu, hjrlib, orc):
                                    f"({r['iterations']}+{r['polish_iterations']} steps; oracle {io['steps']})",
                                    V, Vo, l2)
         assert err <= band and mism == 0
+
+
+def test_quad6_13_cold_fp32_polish_converged(gpu, hjrlib, orc, monkeypatch):
+    """The benchmark's problem on a 13^6 grid (4.8 M nodes, about two minutes of oracle time on
+    16 host threads), cold, with the plane-march kernel the benchmark runs."""
+    p = W.quad6_problem(13, m=1.2, dbar=(0.5, 0.5, 0.5))
+    print("[converged] oracle 13^6 quadrotor solve (cold) ...", flush=True)
+    Vo, io = orc.solve(p.grid, p.dyn, p.l, **orc.problem_opts(p))
+    print(f"[converged]   oracle steps {io['steps']}", flush=True)
+    assert io["converged"] == 1
+    monkeypatch.setenv("HJR_NPT", "-1")
+    opts = hjrlib.problem_options(p, precision=hjrlib.FP32_POLISH64, max_iter=20000)
+    V, r, st = _gpu_solve(hjrlib, gpu, p, None, **opts)
+    assert st == hjrlib.OK
+    err, band, mism = _figures(f"quad6 13^6 cold FP32+polish march ({r['iterations']}+{r['polish_iterations']} steps)",
+                               V, Vo, p.l)
+    assert err <= band and mism == 0
