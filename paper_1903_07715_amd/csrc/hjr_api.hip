@@ -528,11 +528,15 @@ static SolveState initial_state(const Request &r)
 // the plane-march kernel over whole dim-0 lines, -8, -4, -2 = the same in runs of that many
 // planes (more threads; per run, the planes before and after it are read again: two extra loads
 // for upwind, six and one extra dim-0 interface for WENO5).  The march kernels serve groups whose
-// dim-0 planes hold enough columns to fill the device at one thread per column.
+// dim-0 planes hold enough columns to fill the device at one thread per column.  kMarchBrick =
+// the brick variant over whole lines (6-D grids, upwind: pairs of rows of dims 1..3 share their
+// far neighbours through LDS).
 static const int kMarchFull = -1;
 static const int kMarch8 = -8;
+static const int kMarchBrick = -16;
 static const int kFlatSchedule[] = {4, 2, 8, 1, 4};
 static const int kMarchSchedule[] = {4, kMarchFull, 2, 8, 1, kMarch8, 4};
+static const int kMarchBrickSchedule[] = {4, kMarchFull, kMarchBrick, 2, 8, 1, kMarch8, 4};
 // WENO5: runs of 4 or 8 planes (whole lines leave too few threads, runs of 2 pay the run start
 // too often: both measured slower everywhere)
 static const int kMarchW5Schedule[] = {4, -4, 2, 8, kMarch8, 1, 4};
@@ -540,9 +544,21 @@ static const uint64_t kMarchMinColumns = 8192;
 
 static bool valid_config(int c)
 {
-    return c == 1 || c == 2 || c == 4 || c == 8 || c == kMarchFull || c == -2 || c == -4 || c == kMarch8;
+    return c == 1 || c == 2 || c == 4 || c == 8 || c == kMarchFull || c == -2 || c == -4 || c == kMarch8 ||
+           c == kMarchBrick;
 }
 static bool is_march(int c) { return c < 0; }
+
+// Whether the brick kernel serves a grid: 6-D, upwind, and every periodic dim among dims 1..3
+// of even length (the last row of an odd dim has no partner and loads its neighbours itself,
+// which a periodic wrap would need twice).
+static bool brick_ok(const hjr_grid &g, int spatial)
+{
+    if (g.ndim != 6 || spatial != HJR_UPWIND1) return false;
+    for (int d = 1; d <= 3; ++d)
+        if (((g.periodic_mask >> d) & 1u) && (g.n[d] & 1)) return false;
+    return true;
+}
 
 class Tuner {
 public:
@@ -551,18 +567,29 @@ public:
         static Tuner *t = new Tuner();
         return *t;
     }
-    // march: the group may use the plane-march kernel (its candidates are then timed too)
-    static std::string key(int prec, int dyn, int spatial, uint64_t nodes, bool march = false)
+    // march: the group may use the plane-march kernel (its candidates are then timed too);
+    // brick: also the brick variant
+    static std::string key(int prec, int dyn, int spatial, uint64_t nodes, bool march = false, bool brick = false)
     {
         int b = 0;
         while ((2ull << b) <= nodes) ++b;
         char buf[64];
-        snprintf(buf, sizeof buf, "fp%d_dyn%d_sp%d_n2^%d%s", prec ? 64 : 32, dyn, spatial, b, march ? "_m" : "");
+        snprintf(buf, sizeof buf, "fp%d_dyn%d_sp%d_n2^%d%s", prec ? 64 : 32, dyn, spatial, b,
+                 march ? (brick ? "_mb" : "_m") : "");
         return buf;
     }
-    static bool march_key(const std::string &k) { return k.size() > 2 && k.compare(k.size() - 2, 2, "_m") == 0; }
+    static bool ends_with(const std::string &k, const char *x)
+    {
+        const size_t n = strlen(x);
+        return k.size() > n && k.compare(k.size() - n, n, x) == 0;
+    }
+    static bool march_key(const std::string &k) { return ends_with(k, "_m") || ends_with(k, "_mb"); }
     static const int *schedule(const std::string &k, int *len)
     {
+        if (ends_with(k, "_mb")) {
+            *len = (int)(sizeof kMarchBrickSchedule / sizeof kMarchBrickSchedule[0]);
+            return kMarchBrickSchedule;
+        }
         if (march_key(k) && k.find("_sp5_") != std::string::npos) {
             *len = (int)(sizeof kMarchW5Schedule / sizeof kMarchW5Schedule[0]);
             return kMarchW5Schedule;
@@ -1159,6 +1186,7 @@ private:
             uint64_t largest = 0;  // size class for the tuner: the group's largest instance
             uint64_t min_cols = ~0ull;  // the fewest columns (nodes per dim-0 plane) of its grids
             bool march_ok = true;
+            bool brick_ok = true;
         };
         std::map<int, G> groups[2];
         top_slot_ = -1;
@@ -1178,6 +1206,7 @@ private:
             g.min_cols = std::min(g.min_cols, r->npts / (uint64_t)r->grid.n[0]);
             g.march_ok = g.march_ok && (r->opts.spatial == HJR_UPWIND1 || r->opts.spatial == HJR_WENO5) &&
                          r->grid.ndim >= 2 && !r->inst.act;
+            g.brick_ok = g.brick_ok && brick_ok(r->grid, r->opts.spatial);
         }
         if (top_slot_ < 0) top_slot_ = 0;
         std::vector<Tile> t[2];
@@ -1190,6 +1219,7 @@ private:
                 // the march kernel addresses each field with 32-bit byte offsets
                 const bool march_ok = kv.second.march_ok && kv.second.min_cols >= kMarchMinColumns &&
                                       kv.second.largest * (p ? 8ull : 4ull) <= 0xffffffffull;
+                const bool brick = march_ok && kv.second.brick_ok;
                 int cfg = kFusedNpt;
                 std::string tkey;
                 if (local && !fused_) {
@@ -1197,8 +1227,9 @@ private:
                 } else if (!fused_) {
                     cfg = npt_override_;
                     if (cfg && is_march(cfg) && !march_ok) cfg = 4;
+                    if (cfg == kMarchBrick && !brick) cfg = kMarchFull;
                     if (!cfg) {
-                        const std::string k = Tuner::key(p, dyn, sp, kv.second.largest, march_ok);
+                        const std::string k = Tuner::key(p, dyn, sp, kv.second.largest, march_ok, brick);
                         cfg = Tuner::get().choice(k);
                         if (!cfg && autotune_) {
                             cfg = Tuner::get().next_candidate(k);
@@ -1273,7 +1304,10 @@ private:
             Request *r = slots_[i];
             if (r->mtiles_cfg != cfg) {
                 r->mtiles.clear();
-                march_tiles(i, r->grid.ndim, r->grid.n, cfg == kMarchFull ? 0 : -cfg, r->mtiles);
+                if (cfg == kMarchBrick)
+                    march_brick_tiles(i, r->grid.ndim, r->grid.n, r->mtiles);
+                else
+                    march_tiles(i, r->grid.ndim, r->grid.n, cfg == kMarchFull ? 0 : -cfg, r->mtiles);
                 r->mtiles_cfg = cfg;
             }
             out.insert(out.end(), r->mtiles.begin(), r->mtiles.end());
@@ -1353,8 +1387,8 @@ private:
                 if (s != HJR_OK) return s;
             }
             if (is_march(g.npt))
-                HJR_HIP(launch_march(prec != 0, g.dyn, g.spatial, d_insts_, d_mtiles_[prec] + g.moff, g.mcount, stage, stream_,
-                                     ga, gb));
+                HJR_HIP(launch_march(prec != 0, g.dyn, g.spatial, g.npt == kMarchBrick, d_insts_, d_mtiles_[prec] + g.moff,
+                                     g.mcount, stage, stream_, ga, gb));
             else
                 HJR_HIP(launch_stage_one(prec != 0, g.dyn, g.spatial, g.npt, d_insts_, tl + g.off, g.count, stage,
                                          max_blocks_, stream_, ga, gb, g.local));
@@ -2022,11 +2056,15 @@ hjr_status hjr_stage_device(const hjr_grid *grid, const hjr_dynamics *dyn, int32
     const bool march_ok = (spatial == HJR_UPWIND1 || spatial == HJR_WENO5) && grid->ndim >= 2 && cols >= kMarchMinColumns &&
                           r.npts * (f32 ? 4ull : 8ull) <= 0xffffffffull;
     if (is_march(npt) && !march_ok) npt = 0;
-    if (!npt) npt = Tuner::get().choice(Tuner::key(f32 ? 0 : 1, dyn->id, spatial, r.npts, march_ok));
+    const bool bricks = march_ok && brick_ok(*grid, spatial);
+    if (npt == kMarchBrick && !bricks) npt = kMarchFull;
+    if (!npt) npt = Tuner::get().choice(Tuner::key(f32 ? 0 : 1, dyn->id, spatial, r.npts, march_ok, bricks));
     if (!npt || fused) npt = kFusedNpt;
     std::vector<Tile> tiles;
     std::vector<MTile> mtiles;
-    if (is_march(npt)) {
+    if (npt == kMarchBrick) {
+        march_brick_tiles(0, grid->ndim, grid->n, mtiles);
+    } else if (is_march(npt)) {
         march_tiles(0, grid->ndim, grid->n, npt == kMarchFull ? 0 : -npt, mtiles);
     } else {
         for (uint64_t s0 = 0; s0 < r.npts; s0 += (uint64_t)npt * kBlock) tiles.push_back(Tile{0, (uint32_t)s0, npt});
@@ -2042,7 +2080,8 @@ hjr_status hjr_stage_device(const hjr_grid *grid, const hjr_dynamics *dyn, int32
     if (e == hipSuccess) e = hipMemcpyAsync(dtl, tl_host, tl_bytes, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
         if (is_march(npt))
-            e = launch_march(!f32, dyn->id, spatial, dinst, (const MTile *)dtl, (int)mtiles.size(), k, st);
+            e = launch_march(!f32, dyn->id, spatial, npt == kMarchBrick, dinst, (const MTile *)dtl, (int)mtiles.size(),
+                             k, st);
         else if (fused)
             e = launch_stage(!f32, dinst, (const Tile *)dtl, (int)tiles.size(), k, 0, st);
         else

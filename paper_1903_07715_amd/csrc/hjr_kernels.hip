@@ -42,6 +42,7 @@ __device__ __forceinline__ unsigned wave_sum(unsigned v)
 // of workgroups update the same word, so each first reads the word (from L2, relaxed) and
 // issues the atomic only if its value is larger: the word only grows during a launch, so a
 // skipped update was never needed.
+template <int W = kBlock / 64>
 __device__ __forceinline__ double block_max_to(double v, unsigned long long *dst, double *red)
 {
     v = wave_max(v);
@@ -52,7 +53,7 @@ __device__ __forceinline__ double block_max_to(double v, unsigned long long *dst
     if (threadIdx.x == 0) {
         m = red[0];
 #pragma unroll
-        for (int w = 1; w < kBlock / 64; ++w) m = nanmax(m, red[w]);
+        for (int w = 1; w < W; ++w) m = nanmax(m, red[w]);
         const unsigned long long bits = (unsigned long long)__double_as_longlong(m);
         if (m > 0.0 || m != m) {
             const unsigned long long cur = __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -319,6 +320,113 @@ __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, uint
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, soff, 0);
 }
 
+// The fields a plane-march stage reads and writes: S the stage's input, Vn the step-start value
+// (RK3 stages 2 and 3), O the output.  Euler steps alternate between V and A by the step's parity.
+template <typename T> struct MarchFields {
+    const T *S, *Vn;
+    T *O;
+};
+template <typename T>
+__device__ __forceinline__ MarchFields<T> march_fields(const Inst &I, int stage, bool euler)
+{
+    using F = Fields<T>;
+    T *V = F::V(I), *A = F::A(I), *B = F::B(I);
+    if (euler) return I.state->parity ? MarchFields<T>{A, A, V} : MarchFields<T>{V, V, A};
+    if (stage == 0) return MarchFields<T>{V, V, A};
+    if (stage == 1) return MarchFields<T>{A, V, B};
+    return MarchFields<T>{B, V, V};
+}
+
+// The update of one node by the plane-march kernels, in the expressions and order of
+// stage_tile: one-sided differences along dim 0 from the column's previous, current and next
+// values (at a non-periodic end the interior difference stands in for the missing one), along
+// dims 1.. from the loaded neighbours and the edge-rule signs sm, sp; the Hamiltonian with its
+// dissipation; the integrator stage with its projection.  vn is the step-start value (u0 for
+// Euler).
+template <typename T, int DYN, bool EP> struct MarchUpdate {
+    static constexpr int N = DynDim<DYN>::value;
+    const Inst &I;
+    HamCoef<T> kc;
+    T sgn, gm, dt;
+    int n0, stage;
+    bool per0, euler, hasg;
+    T sm[N], sp[N];
+
+    __device__ __forceinline__ T operator()(int i, T um, T u0, T up, const T *un, const T *unp, T lv, T gv,
+                                            T vn) const
+    {
+        using F = Fields<T>;
+        T p[N], diff[N], alpha[N];
+        {
+            T dm = u0 - um, dq = up - u0;
+            if (!per0) {
+                const T r0 = dm, r1 = dq;
+                dm = i == 0 ? r1 : r0;
+                dq = i == n0 - 1 ? r0 : r1;
+            }
+            const T h = F::hinv_dx(I, 0);
+            p[0] = h * (dm + dq);
+            diff[0] = h * (dq - dm);
+        }
+#pragma unroll
+        for (int d = 1; d < N; ++d) {
+            const T dm = sm[d] * (u0 - un[d]);
+            const T dq = sp[d] * (unp[d] - u0);
+            const T h = F::hinv_dx(I, d);
+            p[d] = h * (dm + dq);
+            diff[d] = h * (dq - dm);
+        }
+        T L = ham_eval<T, DYN>(I, kc, p, alpha, sgn);
+#pragma unroll
+        for (int d = 0; d < N; ++d) L += alpha[d] * diff[d];
+        const T s = u0;
+        T out;
+        if (EP) {
+            out = fmin(lv, gm * (s + dt * L));
+        } else if (euler) {
+            out = gm * (s + dt * L);
+            if (!I.brs) out = fmin(lv, out);
+            if (hasg) out = fmax(gv, out);
+        } else if (stage == 0) {
+            out = s + dt * L;
+        } else if (stage == 1) {
+            out = T(0.75) * vn + T(0.25) * (s + dt * L);
+        } else {
+            out = gm * (vn * T(1.0 / 3.0) + T(2.0 / 3.0) * (s + dt * L));
+            if (!I.brs) out = fmin(lv, out);
+            if (hasg) out = fmax(gv, out);
+        }
+        return out;
+    }
+};
+
+// The byte offsets of a node's -/+ neighbours along dim d within the plane (s: the dim's stride
+// in columns) and the signs that apply the edge rule: at a non-periodic end the missing
+// neighbour is replaced by the one on the other side and the difference negated, which gives
+// the interior difference exactly (the rule of line_derivs); periodic dims wrap.
+template <typename T>
+__device__ __forceinline__ void edge_offsets(const Inst &I, int d, int j, uint32_t c, int s, uint32_t &om,
+                                             uint32_t &op, T &sm, T &sp)
+{
+    const int n = I.n[d];
+    int m, q;
+    T a, b;
+    if ((I.periodic >> d) & 1u) {
+        m = j > 0 ? -1 : n - 1;
+        q = j < n - 1 ? 1 : 1 - n;
+        a = b = T(1);
+    } else {
+        m = j > 0 ? -1 : 1;
+        q = j < n - 1 ? 1 : -1;
+        a = j > 0 ? T(1) : T(-1);
+        b = j < n - 1 ? T(1) : T(-1);
+    }
+    om = (uint32_t)((int)c + m * s) * (uint32_t)sizeof(T);
+    op = (uint32_t)((int)c + q * s) * (uint32_t)sizeof(T);
+    sm = a;
+    sp = b;
+}
+
 // EP: the instance takes forward Euler steps projected on l with no constraint function (the
 // common case), so every node makes the same loads; the compiler can then keep the next plane's
 // loads in flight across this plane's arithmetic (a load under a branch makes it wait for all).
@@ -329,28 +437,13 @@ __device__ __forceinline__ void march_tile(const Inst &I, const MTile &tl, int s
     using F = Fields<T>;
     SolveState *st = I.state;
     const bool euler = EP || I.temporal == kEuler;
-    const int par = euler ? st->parity : 0;
-    T *V = F::V(I), *A = F::A(I), *B = F::B(I);
-    const T *S, *Vn;
-    T *O;
-    if (euler) {
-        S = par ? A : V;
-        Vn = S;
-        O = par ? V : A;
-    } else if (stage == 0) {
-        S = V; Vn = V; O = A;
-    } else if (stage == 1) {
-        S = A; Vn = V; O = B;
-    } else {
-        S = B; Vn = V; O = V;
-    }
+    const MarchFields<T> f = march_fields<T>(I, stage, euler);
     const bool last = euler || stage == 2;
     const T *G = EP ? nullptr : uniform_ptr(F::g(I));  // reach-avoid constraint, or nullptr
     const size_t fbytes = (size_t)I.npts * sizeof(T);
-    const __amdgpu_buffer_rsrc_t rS = buf(uniform_ptr(S), fbytes), rVn = buf(uniform_ptr(Vn), fbytes);
-    const __amdgpu_buffer_rsrc_t rO = buf(uniform_ptr(O), fbytes), rl = buf(uniform_ptr(F::l(I)), fbytes);
+    const __amdgpu_buffer_rsrc_t rS = buf(uniform_ptr(f.S), fbytes), rVn = buf(uniform_ptr(f.Vn), fbytes);
+    const __amdgpu_buffer_rsrc_t rO = buf(uniform_ptr(f.O), fbytes), rl = buf(uniform_ptr(F::l(I)), fbytes);
     const __amdgpu_buffer_rsrc_t rG = buf(G, fbytes);
-    const T gm = (T)st->gamma;
     const uint32_t P = I.stride[0];                       // columns (nodes per dim-0 plane)
     const uint32_t pb = P * (uint32_t)sizeof(T);          // bytes per plane
     const int n0 = I.n[0];
@@ -368,41 +461,19 @@ __device__ __forceinline__ void march_tile(const Inst &I, const MTile &tl, int s
             rem = q;
         }
         if (N >= 2) idx[1] = (int)rem;
-        // Byte offsets of the -/+ neighbours within the plane and the sign that applies the
-        // edge rule: at a non-periodic end the missing neighbour is replaced by the one on the
-        // other side and the difference negated, which gives the interior difference exactly
-        // (the rule of line_derivs); periodic dims wrap.
+        MarchUpdate<T, DYN, EP> mu{I, {}, I.game == 0 ? T(1) : T(-1), (T)st->gamma, dt, n0, stage, per0, euler,
+                                   G != nullptr, {}, {}};
         uint32_t om[N], op[N];
-        T sm[N], sp[N];
 #pragma unroll
-        for (int d = 1; d < N; ++d) {
-            const int j = idx[d], n = I.n[d];
-            const int s = d == N - 1 ? 1 : (int)I.stride[d];
-            int m, q;
-            T a, b;
-            if ((I.periodic >> d) & 1u) {
-                m = j > 0 ? -1 : n - 1;
-                q = j < n - 1 ? 1 : 1 - n;
-                a = b = T(1);
-            } else {
-                m = j > 0 ? -1 : 1;
-                q = j < n - 1 ? 1 : -1;
-                a = j > 0 ? T(1) : T(-1);
-                b = j < n - 1 ? T(1) : T(-1);
-            }
-            om[d] = (uint32_t)((int)c + m * s) * (uint32_t)sizeof(T);
-            op[d] = (uint32_t)((int)c + q * s) * (uint32_t)sizeof(T);
-            sm[d] = a;
-            sp[d] = b;
-        }
-        const HamCoef<T> kc = ham_coef<T, DYN>(I, uniform_ptr(F::tab(I)), idx);
-        const T sgn = I.game == 0 ? T(1) : T(-1);
+        for (int d = 1; d < N; ++d)
+            edge_offsets<T>(I, d, idx[d], c, d == N - 1 ? 1 : (int)I.stride[d], om[d], op[d], mu.sm[d], mu.sp[d]);
+        mu.kc = ham_coef<T, DYN>(I, uniform_ptr(F::tab(I)), idx);
         const uint32_t cb = c * (uint32_t)sizeof(T);
         const int i0 = tl.i0, i1 = tl.i0 + tl.len;
         const bool proj = EP || (last && !I.brs);
         const bool useg = !EP && last && G != nullptr;
         // values of S at planes i - 1 and i; at a non-periodic end the centre stands in for the
-        // missing neighbour (its difference is replaced below)
+        // missing neighbour (its difference is replaced in the update)
         const int im = i0 > 0 ? i0 - 1 : (per0 ? n0 - 1 : 0);
         T um = bld<T>(rS, cb, (uint32_t)im * pb);
         T u0 = bld<T>(rS, cb, (uint32_t)i0 * pb);
@@ -429,52 +500,12 @@ __device__ __forceinline__ void march_tile(const Inst &I, const MTile &tl, int s
         // store's offset in a scalar register)
         auto node = [&](int i, uint32_t so, const Cur &c) {
             so = __builtin_amdgcn_readfirstlane(so);
-            const T up = c.up;
-            T p[N], diff[N], alpha[N];
-            {
-                T dm = u0 - um, dq = up - u0;
-                if (!per0) {
-                    const T r0 = dm, r1 = dq;
-                    dm = i == 0 ? r1 : r0;
-                    dq = i == n0 - 1 ? r0 : r1;
-                }
-                const T h = F::hinv_dx(I, 0);
-                p[0] = h * (dm + dq);
-                diff[0] = h * (dq - dm);
-            }
-#pragma unroll
-            for (int d = 1; d < N; ++d) {
-                const T dm = sm[d] * (u0 - c.un[d]);
-                const T dq = sp[d] * (c.unp[d] - u0);
-                const T h = F::hinv_dx(I, d);
-                p[d] = h * (dm + dq);
-                diff[d] = h * (dq - dm);
-            }
-            T L = ham_eval<T, DYN>(I, kc, p, alpha, sgn);
-#pragma unroll
-            for (int d = 0; d < N; ++d) L += alpha[d] * diff[d];
-            const T s = u0;
             const T vn = euler ? u0 : c.vn;
-            T out;
-            if (EP) {
-                out = fmin(c.lv, gm * (s + dt * L));
-            } else if (euler) {
-                out = gm * (s + dt * L);
-                if (!I.brs) out = fmin(c.lv, out);
-                if (G) out = fmax(c.gv, out);
-            } else if (stage == 0) {
-                out = s + dt * L;
-            } else if (stage == 1) {
-                out = T(0.75) * vn + T(0.25) * (s + dt * L);
-            } else {
-                out = gm * (vn * T(1.0 / 3.0) + T(2.0 / 3.0) * (s + dt * L));
-                if (!I.brs) out = fmin(c.lv, out);
-                if (G) out = fmax(c.gv, out);
-            }
+            const T out = mu(i, um, u0, c.up, c.un, c.unp, c.lv, c.gv, vn);
             bst(rO, cb, so, out);
             if (last) delta = nanmax(delta, T(fabs(out - vn)));
             um = u0;
-            u0 = up;
+            u0 = c.up;
         };
         // Two planes per trip, with two sets of load registers used in turn: the next plane's
         // loads go out before this plane's arithmetic, so the loads of two planes are in flight
@@ -517,6 +548,227 @@ __global__ __launch_bounds__(kBlock) void march_kernel(const Inst *__restrict__ 
         march_tile<T, DYN, true>(I, tl, stage, (T)st->dt_cur, red);
     else
         march_tile<T, DYN, false>(I, tl, stage, (T)st->dt_cur, red);
+}
+
+// --------------------------------------------------------------------------------------------
+// Brick variant of the plane-march kernel (6-D grids, first-order upwind)
+//
+// In the march kernel the loads that cost time are those of the far neighbours, along dims 1..3
+// of a 6-D grid (a row of dims 4..5 or more away): they miss the L1 cache and the vector memory
+// pipeline waits on their round trips to L2 and beyond.  Here a workgroup takes a brick of
+// 2 x 2 x 2 rows over dims 1..3 (rows 2k and 2k+1 of each of the three dims) and a segment of
+// kBrickSeg consecutive columns of those rows, and walks its dim-0 line as the march kernel
+// does.  Each plane's centre values also go to LDS, and along each far dim a node takes the
+// neighbour inside its pair of rows from there, so only the neighbour on the other side is
+// loaded from memory: three far loads per node instead of six.  At an end of a dim the edge
+// rule picks the same values as in the march kernel (the partner or the loaded neighbour, and
+// the same sign flips), and the update is MarchUpdate, so the results are the march kernel's
+// bit for bit.  A dim of odd length leaves its last row without a partner; that row loads both
+// of its neighbours from memory (one load: without a partner the row is the dim's last, so a
+// non-periodic end replaces the missing neighbour by the loaded one; the host does not give
+// this kernel a periodic dim of odd length among dims 1..3).  Lanes past the end of a segment,
+// and the rows past the end of a dim, do the loads of the brick's first column and store
+// nothing.
+// --------------------------------------------------------------------------------------------
+constexpr int kBrickSeg = 128;                          // columns per row segment
+constexpr int kBrickRows = 8;                           // 2 x 2 x 2 rows over dims 1..3
+constexpr int kBrickThreads = kBrickSeg * kBrickRows;   // threads per workgroup
+
+// Workgroup barrier for LDS traffic only: the LDS writes before it are complete and visible to
+// the reads after it; loads and stores of global memory still in flight are not waited for.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <typename T, int DYN, bool EP>
+__device__ __forceinline__ void march_brick_tile(const Inst &I, const MTile &tl, int stage, T dt, double *red,
+                                                 T (*lds)[kBrickRows][kBrickSeg])
+{
+    constexpr int N = DynDim<DYN>::value;
+    static_assert(N == 6, "bricks pair the rows of dims 1..3 of a 6-D grid");
+    using F = Fields<T>;
+    SolveState *st = I.state;
+    const bool euler = EP || I.temporal == kEuler;
+    const MarchFields<T> f = march_fields<T>(I, stage, euler);
+    const bool last = euler || stage == 2;
+    const T *G = EP ? nullptr : uniform_ptr(F::g(I));
+    const size_t fbytes = (size_t)I.npts * sizeof(T);
+    const __amdgpu_buffer_rsrc_t rS = buf(uniform_ptr(f.S), fbytes), rVn = buf(uniform_ptr(f.Vn), fbytes);
+    const __amdgpu_buffer_rsrc_t rO = buf(uniform_ptr(f.O), fbytes), rl = buf(uniform_ptr(F::l(I)), fbytes);
+    const __amdgpu_buffer_rsrc_t rG = buf(G, fbytes);
+    const uint32_t pb = I.stride[0] * (uint32_t)sizeof(T);  // bytes per plane
+    const int n0 = I.n[0];
+    const bool per0 = I.periodic & 1u;
+    // the row is the same in a wave (a wave is 64 columns of one row); saying so keeps everything
+    // that depends only on the row (its indices along dims 1..3, edge rule, partner) scalar
+    const int row = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kBrickSeg);
+    const int sx = (int)threadIdx.x % kBrickSeg;
+    // indices of the brick's first column (the same in every lane)
+    int base[N];
+    {
+        uint32_t rem = tl.c0;
+#pragma unroll
+        for (int d = N - 1; d >= 2; --d) {
+            const uint32_t q = fdiv(rem, I.div[d]);
+            base[d] = (int)(rem - q * (uint32_t)I.n[d]);
+            rem = q;
+        }
+        base[1] = (int)rem;
+    }
+    int e[4];  // this row's place in its pair along dims 1..3
+    e[1] = (row >> 2) & 1;
+    e[2] = (row >> 1) & 1;
+    e[3] = row & 1;
+    bool rowok = true;
+#pragma unroll
+    for (int d = 1; d <= 3; ++d) rowok = rowok && base[d] + e[d] < I.n[d];
+    // lanes past the segment's end work on its last column; a row past a dim's end on the
+    // brick's first column (valid addresses either way; neither stores)
+    const bool active = rowok && sx < (int)tl.cn;
+    const int sc = sx < (int)tl.cn ? sx : (int)tl.cn - 1;
+    int idx[N];
+    uint32_t c = tl.c0;
+    idx[0] = 0;
+#pragma unroll
+    for (int d = 1; d < N; ++d) idx[d] = base[d];
+    if (rowok) {
+        c += (uint32_t)(e[1] * (int)I.stride[1] + e[2] * (int)I.stride[2] + e[3] * (int)I.stride[3] + sc);
+#pragma unroll
+        for (int d = 1; d <= 3; ++d) idx[d] += e[d];
+        const uint32_t r = (uint32_t)(base[4] * I.n[5] + base[5] + sc);  // position within the row
+        const uint32_t q = fdiv(r, I.div[5]);
+        idx[4] = (int)q;
+        idx[5] = (int)(r - q * (uint32_t)I.n[5]);
+    }
+    MarchUpdate<T, DYN, EP> mu{I, {}, I.game == 0 ? T(1) : T(-1), (T)st->gamma, dt, n0, stage, per0, euler,
+                               G != nullptr, {}, {}};
+    // far dims: the byte offset of the neighbour loaded from memory, and which sides take the
+    // partner row's value from LDS instead (all of it the same across a wave)
+    uint32_t og[4];
+    bool ml[4], pl[4];
+#pragma unroll
+    for (int d = 1; d <= 3; ++d) {
+        const int j = idx[d], n = I.n[d];
+        const bool per = (I.periodic >> d) & 1u;
+        int q = 0;
+        bool m = false, p = false;
+        T a = T(1), b = T(1);
+        if (!rowok) {
+        } else if (e[d]) {  // the partner is j - 1
+            m = true;
+            if (j + 1 < n) q = 1;
+            else if (per) q = 1 - n;
+            else { p = true; b = T(-1); }
+        } else if (j + 1 < n) {  // the partner is j + 1
+            p = true;
+            if (j > 0) q = -1;
+            else if (per) q = n - 1;
+            else { m = true; a = T(-1); }
+        } else {  // the dim's last row, without a partner (non-periodic)
+            q = -1;
+            b = T(-1);
+        }
+        og[d] = (uint32_t)((int)c + q * (int)I.stride[d]) * (uint32_t)sizeof(T);
+        ml[d] = m;
+        pl[d] = p;
+        mu.sm[d] = a;
+        mu.sp[d] = b;
+    }
+    uint32_t om[N], op[N];
+#pragma unroll
+    for (int d = 4; d < N; ++d)
+        edge_offsets<T>(I, d, idx[d], c, d == N - 1 ? 1 : (int)I.stride[d], om[d], op[d], mu.sm[d], mu.sp[d]);
+    mu.kc = ham_coef<T, DYN>(I, uniform_ptr(F::tab(I)), idx);
+    const uint32_t cb = c * (uint32_t)sizeof(T);
+    const int i0 = tl.i0, i1 = tl.i0 + tl.len;
+    const bool proj = EP || (last && !I.brs);
+    const bool useg = !EP && last && G != nullptr;
+    const int im = i0 > 0 ? i0 - 1 : (per0 ? n0 - 1 : 0);
+    T um = bld<T>(rS, cb, (uint32_t)im * pb);
+    T u0 = bld<T>(rS, cb, (uint32_t)i0 * pb);
+    T delta = T(0);
+    struct Cur {
+        T up, g[4], un[N], unp[N], lv, gv, vn;
+    };
+    auto load_plane = [&](int i, uint32_t so) {
+        Cur c;
+        const uint32_t sp1 = i + 1 < n0 ? so + pb : (per0 ? 0u : so);
+        c.up = bld<T>(rS, cb, sp1);
+#pragma unroll
+        for (int d = 1; d <= 3; ++d) c.g[d] = bld<T>(rS, og[d], so);
+#pragma unroll
+        for (int d = 4; d < N; ++d) {
+            c.un[d] = bld<T>(rS, om[d], so);
+            c.unp[d] = bld<T>(rS, op[d], so);
+        }
+        c.lv = proj ? bld<T>(rl, cb, so) : T(0);
+        c.gv = useg ? bld<T>(rG, cb, so) : T(0);
+        c.vn = euler ? T(0) : bld<T>(rVn, cb, so);
+        return c;
+    };
+    // the node at plane i: its centre value goes to the plane's LDS buffer (two buffers, used by
+    // alternate planes, so one barrier per plane suffices), then the partner rows' values come back
+    auto node = [&](int i, uint32_t so, Cur &c) {
+        so = __builtin_amdgcn_readfirstlane(so);
+        T(*b)[kBrickSeg] = lds[i & 1];
+        b[row][sx] = u0;
+        lds_barrier();
+#pragma unroll
+        for (int d = 1; d <= 3; ++d) {
+            const T v = b[row ^ (4 >> (d - 1))][sx];
+            c.un[d] = ml[d] ? v : c.g[d];
+            c.unp[d] = pl[d] ? v : c.g[d];
+        }
+        const T vn = euler ? u0 : c.vn;
+        const T out = mu(i, um, u0, c.up, c.un, c.unp, c.lv, c.gv, vn);
+        if (active) {
+            bst(rO, cb, so, out);
+            if (last) delta = nanmax(delta, T(fabs(out - vn)));
+        }
+        um = u0;
+        u0 = c.up;
+    };
+    // two planes per trip with two sets of load registers, as in march_tile; every lane makes the
+    // same number of trips, so the barriers match
+    uint32_t so = (uint32_t)i0 * pb;
+    Cur ca = load_plane(i0, so);
+    for (int i = i0; i < i1; i += 2, so += 2 * pb) {
+        const int ib = i + 1 < i1 ? i + 1 : i;
+        Cur cn = load_plane(ib, (uint32_t)ib * pb);
+        asm volatile("" ::: "memory");
+        node(i, so, ca);
+        if (i + 1 >= i1) break;
+        const int ia = i + 2 < i1 ? i + 2 : i + 1;
+        ca = load_plane(ia, (uint32_t)ia * pb);
+        asm volatile("" ::: "memory");
+        node(i + 1, so + pb, cn);
+    }
+    if (last) block_max_to<kBrickThreads / 64>((double)delta, &st->delta_bits, red);
+}
+
+// FP32: at most 64 VGPRs, so that two workgroups (8 waves per SIMD) fit on a CU
+template <typename T, int DYN>
+__global__ __launch_bounds__(kBrickThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4)))
+void march_brick_kernel(const Inst *__restrict__ insts,
+                                                                    const MTile *__restrict__ tiles, int ntiles,
+                                                                    int stage)
+{
+    __shared__ double red[kBrickThreads / 64];
+    __shared__ T lds[2][kBrickRows][kBrickSeg];
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const MTile tl = tiles[t];
+    if (tl.cn == 0) return;  // padding
+    const Inst &I = insts[tl.inst];
+    const SolveState *st = I.state;
+    if (st->done != kRunning || stage >= I.nstages) return;
+    if (I.temporal == kEuler && !I.brs && Fields<T>::g(I) == nullptr)
+        march_brick_tile<T, DYN, true>(I, tl, stage, (T)st->dt_cur, red, lds);
+    else
+        march_brick_tile<T, DYN, false>(I, tl, stage, (T)st->dt_cur, red, lds);
 }
 
 // --------------------------------------------------------------------------------------------
@@ -1101,16 +1353,23 @@ hipError_t launch_stage_one(bool fp64, int dyn, int spatial, int npt, const Inst
 }
 
 template <typename T>
-static void launch_march_t(int dyn, int spatial, dim3 g, hipStream_t s, const Inst *insts, const MTile *tiles,
-                           int ntiles, int stage, hipEvent_t ev0, hipEvent_t ev1)
+static hipError_t launch_march_t(int dyn, int spatial, bool brick, dim3 g, hipStream_t s, const Inst *insts,
+                                 const MTile *tiles, int ntiles, int stage, hipEvent_t ev0, hipEvent_t ev1)
 {
-#define HJR_MARCH_K(K)                                                                                         \
+#define HJR_MARCH_KB(K, B)                                                                                     \
     do {                                                                                                       \
         if (ev0 || ev1)                                                                                        \
-            hipExtLaunchKernelGGL((K), g, dim3(kBlock), 0, s, ev0, ev1, 0u, insts, tiles, ntiles, stage);      \
+            hipExtLaunchKernelGGL((K), g, dim3(B), 0, s, ev0, ev1, 0u, insts, tiles, ntiles, stage);           \
         else                                                                                                   \
-            hipLaunchKernelGGL((K), g, dim3(kBlock), 0, s, insts, tiles, ntiles, stage);                       \
+            hipLaunchKernelGGL((K), g, dim3(B), 0, s, insts, tiles, ntiles, stage);                            \
     } while (0)
+#define HJR_MARCH_K(K) HJR_MARCH_KB(K, kBlock)
+    if (brick) {
+        // bricks exist for the 6-D model with the upwind stencil only
+        if (dyn != kDynQuad || spatial != kUpwind1) return hipErrorInvalidValue;
+        HJR_MARCH_KB((march_brick_kernel<T, kDynQuad>), kBrickThreads);
+        return hipSuccess;
+    }
 #define HJR_MARCH(D)                                                                                           \
     do {                                                                                                       \
         if (spatial == kWeno5)                                                                                 \
@@ -1129,6 +1388,27 @@ static void launch_march_t(int dyn, int spatial, dim3 g, hipStream_t s, const In
     }
 #undef HJR_MARCH
 #undef HJR_MARCH_K
+#undef HJR_MARCH_KB
+    return hipSuccess;
+}
+
+// Rounds of 8 blocks, one per XCD, interleaved workgroup by workgroup; the blocks are taken
+// largest first (the blocks at the high ends of the index ranges are smaller) so that the
+// blocks of a round are of about the same size and little padding is needed; a last round of
+// fewer blocks is appended in plain order.
+static void interleave_blocks(int inst, std::vector<std::vector<MTile>> &blocks, std::vector<MTile> &out)
+{
+    std::stable_sort(blocks.begin(), blocks.end(),
+                     [](const std::vector<MTile> &a, const std::vector<MTile> &b) { return a.size() > b.size(); });
+    const size_t nb8 = blocks.size() / 8 * 8;
+    for (size_t r = 0; r < nb8; r += 8) {
+        size_t m = 0;
+        for (size_t x = 0; x < 8; ++x) m = std::max(m, blocks[r + x].size());
+        for (size_t k = 0; k < m; ++k)
+            for (size_t x = 0; x < 8; ++x)
+                out.push_back(k < blocks[r + x].size() ? blocks[r + x][k] : MTile{inst, 0u, 0, 0, 0u});
+    }
+    for (size_t r = nb8; r < blocks.size(); ++r) out.insert(out.end(), blocks[r].begin(), blocks[r].end());
 }
 
 void march_tiles(int inst, int ndim, const int *n, int len, std::vector<MTile> &out)
@@ -1176,33 +1456,47 @@ void march_tiles(int inst, int ndim, const int *n, int len, std::vector<MTile> &
                         }
                 blocks.push_back(std::move(blk));
             }
-    // rounds of 8 blocks, one per XCD, interleaved workgroup by workgroup; the blocks are taken
-    // largest first (the blocks at the high ends of the index ranges are smaller) so that the
-    // blocks of a round are of about the same size and little padding is needed; a last round of
-    // fewer blocks is appended in plain order
-    std::stable_sort(blocks.begin(), blocks.end(),
-                     [](const std::vector<MTile> &a, const std::vector<MTile> &b) { return a.size() > b.size(); });
-    const size_t nb8 = blocks.size() / 8 * 8;
-    for (size_t r = 0; r < nb8; r += 8) {
-        size_t m = 0;
-        for (size_t x = 0; x < 8; ++x) m = std::max(m, blocks[r + x].size());
-        for (size_t k = 0; k < m; ++k)
-            for (size_t x = 0; x < 8; ++x)
-                out.push_back(k < blocks[r + x].size() ? blocks[r + x][k] : MTile{inst, 0u, 0, 0, 0u});
-    }
-    for (size_t r = nb8; r < blocks.size(); ++r) out.insert(out.end(), blocks[r].begin(), blocks[r].end());
+    interleave_blocks(inst, blocks, out);
 }
 
-hipError_t launch_march(bool fp64, int dyn, int spatial, const Inst *insts, const MTile *tiles, int ntiles,
-                        int stage, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+void march_brick_tiles(int inst, int ndim, const int *n, std::vector<MTile> &out)
+{
+    if (ndim != 6) return;
+    const uint64_t R = (uint64_t)n[4] * n[5];            // columns per row
+    const uint64_t s3 = R, s2 = (uint64_t)n[3] * s3, s1 = (uint64_t)n[2] * s2;
+    const uint64_t segs = (R + kBrickSeg - 1) / kBrickSeg;
+    const uint64_t q1 = (n[1] + 1) / 2, q2 = (n[2] + 1) / 2, q3 = (n[3] + 1) / 2;  // row pairs per dim
+    // blocks of about 64 bricks (the workgroups an XCD holds at two per CU): all segments of
+    // 2 x 2 x B3 neighbouring bricks
+    const uint64_t B1 = std::min<uint64_t>(2, q1), B2 = std::min<uint64_t>(2, q2);
+    const uint64_t k = B1 * B2 * segs;
+    const uint64_t B3 = std::min<uint64_t>(q3, std::max<uint64_t>(1, (64 + k / 2) / k));
+    std::vector<std::vector<MTile>> blocks;
+    for (uint64_t a0 = 0; a0 < q1; a0 += B1)
+        for (uint64_t b0 = 0; b0 < q2; b0 += B2)
+            for (uint64_t c0 = 0; c0 < q3; c0 += B3) {
+                std::vector<MTile> blk;
+                for (uint64_t a = a0; a < std::min(q1, a0 + B1); ++a)
+                    for (uint64_t b = b0; b < std::min(q2, b0 + B2); ++b)
+                        for (uint64_t c = c0; c < std::min(q3, c0 + B3); ++c)
+                            for (uint64_t g = 0; g < segs; ++g) {
+                                const uint64_t col = 2 * a * s1 + 2 * b * s2 + 2 * c * s3 + g * kBrickSeg;
+                                const uint32_t cn = (uint32_t)std::min<uint64_t>(kBrickSeg, R - g * kBrickSeg);
+                                blk.push_back(MTile{inst, (uint32_t)col, 0, n[0], cn});
+                            }
+                blocks.push_back(std::move(blk));
+            }
+    interleave_blocks(inst, blocks, out);
+}
+
+hipError_t launch_march(bool fp64, int dyn, int spatial, bool brick, const Inst *insts, const MTile *tiles,
+                        int ntiles, int stage, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (ntiles <= 0) return hipSuccess;
     const dim3 g(ntiles);
-    if (fp64)
-        launch_march_t<double>(dyn, spatial, g, s, insts, tiles, ntiles, stage, ev0, ev1);
-    else
-        launch_march_t<float>(dyn, spatial, g, s, insts, tiles, ntiles, stage, ev0, ev1);
-    return hipGetLastError();
+    const hipError_t e = fp64 ? launch_march_t<double>(dyn, spatial, brick, g, s, insts, tiles, ntiles, stage, ev0, ev1)
+                              : launch_march_t<float>(dyn, spatial, brick, g, s, insts, tiles, ntiles, stage, ev0, ev1);
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t launch_step_end(const Inst *insts, int ninst, hipStream_t s)

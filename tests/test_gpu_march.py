@@ -8,7 +8,9 @@ neighbours (upwind) or dim-0 differences and interfaces (WENO5) carried in regis
 output and every max-change reduction must be bitwise identical to the flat kernel's, for every
 scheme, model, game, precision, integrator stage, ragged grid, periodic dimension (dim 0
 included) and run length (whole lines, and runs of 8, 4 and 2 planes, whose ends fall at
-different distances from the grid's edges).  The oracle then pins the common result (FP64:
+different distances from the grid's edges).  Configuration -16, the brick variant (pairs of rows
+of dims 1..3 sharing their far neighbours through LDS), serves the 6-D upwind cases; elsewhere
+the library runs the whole-line march kernel for it.  The oracle then pins the common result (FP64:
 1e-12, FP32: 2e-5 of the field's scale, as in the stage parity tests).
 """
 import math
@@ -25,6 +27,10 @@ SEED = W.SEED
 def _cases():
     # every grid has at least 8192 columns (nodes per dim-0 plane), the march kernel's minimum
     quad = W.Grid((7, 9, 11, 13, 8, 10), (-5, -5, -5, -3, -3, -3), (5, 5, 5, 3, 3, 3))
+    # periodic dims 1 and 3 (even lengths) and an odd non-periodic dim 2 between them; rows of
+    # 9 x 31 = 279 columns, so the brick kernel's segments are 128, 128 and 23 columns long
+    quadper = W.Grid((7, 8, 7, 8, 9, 31), (-5, -5, -5, -3, -3, -3), (5, 5, 5, 3, 3, 3),
+                     (False, True, False, True, False, False))
     q10xy = W.Grid((13, 41, 23, 17), (-6.0, -4.0, -0.4, -4.0), (6.0, 4.0, 0.4, 4.0))
     uni = W.Grid((9, 31, 24, 15), (-5.0, -5.0, -math.pi, 0.0), (5.0, 5.0, math.pi, 2.0), (False, False, True, False))
     dub = W.Grid((21, 97, 101), (-5.0, -5.0, -math.pi), (5.0, 5.0, math.pi), (False, False, True))
@@ -32,6 +38,7 @@ def _cases():
     q10z = W.Grid((11, 8193), (-2.0, -6.0), (8.0, 6.0))
     return [
         ("quad6", quad, W.quad6(1.2, (0.5, 0.3, 0.4))),
+        ("quad6-periodic", quadper, W.quad6(1.2, (0.5, 0.3, 0.4))),
         ("quad10-xy", q10xy, W.quad10_xy(1.2)),
         ("unicycle", uni, W.unicycle4(1.0, 0.5, 0.1)),
         ("dubins", dub, W.dubins3(1.0, 1.5, 0.1, 0.05)),
@@ -81,7 +88,7 @@ def test_march_stage_bitwise_equals_flat_and_matches_oracle(gpu, hjrlib, orc, mo
         src = t_vn if stage == 1 else t_vs
         flat, dflat = _run_stage(hjrlib, monkeypatch, "4", g, d, stage, dt, src, t_vn, t_l, temporal, prec, game,
                                  spatial)
-        for cfg in ("-1", "-8", "-4", "-2"):
+        for cfg in ("-1", "-8", "-4", "-2", "-16"):
             got, dgot = _run_stage(hjrlib, monkeypatch, cfg, g, d, stage, dt, src, t_vn, t_l, temporal, prec, game,
                                    spatial)
             assert torch.equal(got, flat), (name, stage, cfg, float((got.double() - flat.double()).abs().max()))
@@ -106,7 +113,7 @@ def test_march_solves_bitwise_equal_flat(gpu, hjrlib, monkeypatch):
     K = torch.empty_like(lt)
     hjrlib.solve_device(q.grid, q.dyn, lt, None, K, **opts)
     results = {}
-    for cfg in ("4", "-1", "-8"):
+    for cfg in ("4", "-1", "-8", "-16"):
         monkeypatch.setenv("HJR_NPT", cfg)
         for warm in (False, True):
             V = torch.empty_like(lt)
@@ -115,7 +122,7 @@ def test_march_solves_bitwise_equal_flat(gpu, hjrlib, monkeypatch):
                   flush=True)
             assert st == hjrlib.OK
             results[(cfg, warm)] = (r["iterations"], r["polish_iterations"], V.cpu())
-    for cfg in ("-1", "-8"):
+    for cfg in ("-1", "-8", "-16"):
         for warm in (False, True):
             a, b = results[("4", warm)], results[(cfg, warm)]
             assert a[:2] == b[:2] and torch.equal(a[2], b[2])
