@@ -63,6 +63,35 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def tuner_config(fp64: bool, dyn_id: int, spatial: int, nodes: int):
+    """The launch configuration the library uses for a group of this size class: HJR_NPT when
+    set, else the tuner's choice from its cache file (HJR_TUNE_CACHE, which main() points at a
+    fresh file unless the caller set one), or None before the tuner has chosen."""
+    if os.environ.get("HJR_NPT"):
+        return int(os.environ["HJR_NPT"])
+    path = os.environ.get("HJR_TUNE_CACHE")
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        choices = json.load(f)
+    key = f"fp{64 if fp64 else 32}_dyn{dyn_id}_sp{spatial}_n2^{int(nodes).bit_length() - 1}"
+    for k, v in choices.items():
+        if k == key or k.startswith(key + "_"):
+            return int(v)
+    return None
+
+
+def kernel_name(cfg, fp64: bool, model: str, scheme: str = "upwind"):
+    t = "double" if fp64 else "float"
+    if cfg == -16:
+        return f"march_brick_kernel<{t}, {model}> (2 x 2 x 2 row bricks, whole lines)"
+    if cfg is not None and cfg < 0:
+        return f"march_kernel<{t}, {model}> ({'whole lines' if cfg == -1 else f'runs of {-cfg} planes'})"
+    if cfg:
+        return f"stage_kernel_one<{t}, {model}, {scheme}, {cfg} nodes per thread>"
+    return "the stage kernel the tuner keeps"
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +172,10 @@ def cpu_baseline(p, npts, seconds):
 
 def main():
     args = parse()
+    if not os.environ.get("HJR_TUNE_CACHE"):
+        import tempfile
+
+        os.environ["HJR_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="hjr_tune_"), "choices.json")
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -301,10 +334,12 @@ def bench_quad6(args):
     roofline = {"bound": "hbm", "achieved": round(gbs32, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(gbs32 / PEAK_HBM_GBS, 4),
                 "traffic": MEASURED_TRAFFIC.get(kernel_source_hash(), {}).get("quad6") if n == 25 else None,
-                "kernel": "march_kernel<float, Quad6> (upwind + Lax-Friedrichs + Euler step, FP32)",
+                "kernel": kernel_name(tuner_config(False, p.dyn.id, 1, npts), False, "Quad6")
+                + ": upwind + Lax-Friedrichs + Euler step, FP32",
                 "bytes_per_update": BYTES_PER_NODE_STEP_EULER_FP32,
                 "avg_launch_us": round(avg32 * 1e6, 1), "working_launches": n32,
-                "fp64_polish_kernel": {"achieved": round(gbs64, 1), "frac": round(gbs64 / PEAK_HBM_GBS, 4),
+                "fp64_polish_kernel": {"kernel": kernel_name(tuner_config(True, p.dyn.id, 1, npts), True, "Quad6"),
+                                       "achieved": round(gbs64, 1), "frac": round(gbs64 / PEAK_HBM_GBS, 4),
                                        "bytes_per_update": BYTES_PER_NODE_STEP_EULER_FP64,
                                        "avg_launch_us": round(avg64 * 1e6, 1), "working_launches": n64}}
     line = {
@@ -838,7 +873,7 @@ def bench_hbm(args):
                       "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                    "frac": round(gbs / PEAK_HBM_GBS, 4), "avg_launch_us": round(avg_s * 1e6, 1),
                                    "working_launches": nwork,
-                                   "kernel": "the FP32 upwind + LF + Euler stage kernel the tuner keeps"}}),
+                                   "kernel": kernel_name(tuner_config(False, p.dyn.id, 1, npts), False, "Quad6")}}),
           flush=True)
 
 

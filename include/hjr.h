@@ -323,6 +323,18 @@ typedef struct {
 hjr_status hjr_profile_enable(int32_t on);
 hjr_status hjr_profile_read(hjr_profile *out, int32_t reset);
 
+/* Launch plan (host only, touches no device): the tiles the plane-march kernels take for one
+ * grid under launch configuration `config`, in launch order (workgroup t takes tile t and runs
+ * on XCD t mod 8).  config: -1 whole dim-0 lines; -2, -4, -8 runs of that many planes; -16 the
+ * brick variant (6-D grids whose periodic dims among dims 1..3 have even lengths).  Tile t goes
+ * to out[5t .. 5t+4]: its first column (flat index within a dim-0 plane), first plane, number of
+ * planes, number of columns (0: a padding tile that does nothing), and number of rows (1; 8 for a
+ * brick, whose rows are 2k, 2k+1 along each of dims 1..3 from the first column's row, those
+ * beyond a dim's end left out).  Writes at most `cap` tiles (out may be NULL when cap is 0);
+ * returns the number of tiles, or a negative hjr_status (HJR_ERR_INVALID_ARG for a bad grid or
+ * configuration). */
+int64_t hjr_march_plan(const hjr_grid *grid, int32_t config, int64_t *out, int64_t cap);
+
 /* ---------------------------------------------------------------------------------------------
  * Safe control (Sec. II-B.2, eq. (uOpt)): online, the system applies
  * u*(x) = argmax_u min_d <grad V(x), f(x, u, d)> with V the converged value function (avoid game;

@@ -1945,6 +1945,32 @@ hjr_status hjr_profile_read(hjr_profile *out, int32_t reset)
     return HJR_OK;
 }
 
+int64_t hjr_march_plan(const hjr_grid *grid, int32_t config, int64_t *out, int64_t cap)
+{
+    uint64_t npts = 0;
+    hjr_status st = validate_grid(grid, HJR_UPWIND1, &npts);
+    if (st != HJR_OK) return st;
+    if (!is_march(config) || !valid_config(config) || grid->ndim < 2 || cap < 0 || (cap > 0 && !out))
+        return fail(HJR_ERR_INVALID_ARG, "bad march configuration %d, ndim %d or output", config, grid->ndim);
+    std::vector<MTile> m;
+    if (config == kMarchBrick) {
+        if (!brick_ok(*grid, HJR_UPWIND1))
+            return fail(HJR_ERR_INVALID_ARG, "bricks need a 6-D grid whose periodic dims among 1..3 have even lengths");
+        march_brick_tiles(0, grid->ndim, grid->n, m);
+    } else {
+        march_tiles(0, grid->ndim, grid->n, config == kMarchFull ? 0 : -config, m);
+    }
+    const int64_t rows = config == kMarchBrick ? 8 : 1;
+    for (int64_t t = 0; t < (int64_t)m.size() && t < cap; ++t) {
+        out[5 * t + 0] = m[t].c0;
+        out[5 * t + 1] = m[t].i0;
+        out[5 * t + 2] = m[t].len;
+        out[5 * t + 3] = m[t].cn;
+        out[5 * t + 4] = rows;
+    }
+    return (int64_t)m.size();
+}
+
 // ---------------------------------------------------------------------------------------------
 // Kernel-level entry points
 // ---------------------------------------------------------------------------------------------

@@ -32,7 +32,7 @@ EXPORTED = ["hjr_abi_version", "hjr_build_id", "hjr_default_options", "hjr_statu
             "hjr_stage_device", "hjr_ctx_create", "hjr_submit", "hjr_poll", "hjr_ctx_drain",
             "hjr_ctx_get_stats", "hjr_ctx_destroy", "hjr_profile_enable", "hjr_profile_read",
             "hjr_num_controls", "hjr_gradient_device", "hjr_safe_control_device", "hjr_solve_reach_avoid",
-            "hjr_solve_reach_avoid_device", "hjr_local_dependencies"]
+            "hjr_solve_reach_avoid_device", "hjr_local_dependencies", "hjr_march_plan"]
 
 
 class Grid_(C.Structure):
@@ -124,6 +124,7 @@ def load():
         lib.hjr_batch_solve.argtypes = [C.c_int32, P(Problem_)]
         lib.hjr_local_dependencies.argtypes = [P(Grid_), C.c_int32, P(C.c_int64), P(C.c_int64), vp, vp]
         lib.hjr_cfl_dt.argtypes = [P(Grid_), P(Dynamics_), C.c_double, C.c_double, dp]
+        lib.hjr_march_plan.argtypes = [P(Grid_), C.c_int32, P(C.c_int64), C.c_int64]
         lib.hjr_stage_device.argtypes = [P(Grid_), P(Dynamics_), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                          C.c_int32, C.c_double, vp, vp, vp, vp, dp, vp]
         lib.hjr_ctx_create.argtypes = [C.c_int32, C.c_size_t, P(vp)]
@@ -140,8 +141,9 @@ def load():
                                                 vp]
         for name in EXPORTED:
             if name not in ("hjr_status_string", "hjr_last_error", "hjr_abi_version", "hjr_build_id", "hjr_device_count",
-                            "hjr_num_controls"):
+                            "hjr_num_controls", "hjr_march_plan"):
                 getattr(lib, name).restype = C.c_int32
+        lib.hjr_march_plan.restype = C.c_int64
         _lib = lib
     return _lib
 
@@ -348,6 +350,20 @@ def local_dependencies(grid, reach: int):
     dep = np.empty(max(nd.value, 1), dtype=np.uint32)
     _check(load().hjr_local_dependencies(C.byref(gs), reach, C.byref(nb), C.byref(nd), off.ctypes.data, dep.ctypes.data))
     return off, dep[:nd.value]
+
+
+def march_plan(grid, config: int) -> np.ndarray:
+    """hjr_march_plan: the march tiles for `grid` under launch configuration `config`, in launch
+    order, as an int64 array of rows (first column, first plane, planes, columns, rows)."""
+    gs = grid_struct(grid)
+    n = load().hjr_march_plan(C.byref(gs), config, None, 0)
+    if n < 0:
+        _check(int(n))
+    out = np.zeros((max(n, 1), 5), dtype=np.int64)
+    m = load().hjr_march_plan(C.byref(gs), config, out.ctypes.data_as(C.POINTER(C.c_int64)), n)
+    if m != n:
+        raise HJRError(ERR_INVALID_ARG, "march plan changed between calls")
+    return out[:n]
 
 
 def cfl_dt(grid, dyn, cfl=0.5, dt_max=0.0) -> float:
