@@ -42,11 +42,11 @@ BYTES_PER_NODE_STEP_EULER_FP64 = 24
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (packed FMA) peak
 PEAK_HBM_GBS = 8000.0
 
-# Bytes per launch of the headline's FP32 stage kernel (the plane-march kernel on the 25^6
+# Bytes per launch of the headline's FP32 stage kernel (the brick plane-march kernel on the 25^6
 # quadrotor) between L2 and memory, from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a
 # 1 GiB copy calibration (profiles/quad6_25_headline_hbm_counters.txt), keyed by a hash of the
 # kernel sources they were taken from: a kernel changed since then reports null.
-MEASURED_TRAFFIC = {"797acc227a18ad70": {"quad6": 4.973e9 + 1.041e9}}
+MEASURED_TRAFFIC = {"d16faf77ceee9f54": {"quad6": 4.094e9 + 1.008e9}}
 
 
 def kernel_source_hash() -> str:
