@@ -3,7 +3,10 @@
     python -m paper_1903_07715_amd.build        # or: from paper_1903_07715_amd.build import build
 
 Every HIP source is compiled for gfx950 only, with packed FP32 instructions disabled
-(-target-feature -packed-fp32-ops), and linked into paper_1903_07715_amd/libhjr.so.
+(-target-feature -packed-fp32-ops) and floating-point contraction only within one expression
+(-ffp-contract=on: an a * b + c written in one expression becomes a fused multiply-add, nothing
+across statements does), so the rounding of the arithmetic the kernel variants share is fixed by
+the source and every variant produces the same bits; linked into paper_1903_07715_amd/libhjr.so.
 """
 from __future__ import annotations
 
@@ -30,7 +33,7 @@ def hipcc() -> str:
 
 def flags() -> list:
     return ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall", "-Wno-unused-function",
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-ffp-contract=on", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 

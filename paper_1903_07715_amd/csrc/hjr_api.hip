@@ -1800,11 +1800,17 @@ static hjr_status scratch_address(int dev, void **out)
 
 // Scratch bytes a single solve's engine may take: the state and descriptor, the request's
 // working arrays, and the flat and march tile lists of both precisions (the engine keeps room
-// for twice the tiles it lists; the bound takes one tile per 256 nodes, the most any
-// configuration lists, plus padding of the march order).
+// for twice the tiles it lists; the bound takes one tile per 256 nodes, the most the flat and
+// march configurations list, plus padding of the march order, or the brick plan's own length
+// where that is longer: its padding depends on how the grid's row pairs fall into blocks).
 static size_t noalloc_bytes(const Request &r)
 {
-    const size_t tiles = (size_t)((r.npts + kBlock - 1) / kBlock) + 8 * kBlock;
+    size_t tiles = (size_t)((r.npts + kBlock - 1) / kBlock) + 8 * kBlock;
+    if (brick_ok(r.grid, r.opts.spatial)) {
+        std::vector<MTile> m;
+        march_brick_tiles(0, r.grid.ndim, r.grid.n, m);
+        tiles = std::max(tiles, m.size());
+    }
     const size_t list = align256(std::max(2 * tiles * sizeof(MTile), (size_t)4096));
     return align256(sizeof(SolveState)) + align256(sizeof(Inst)) + request_bytes(r, false) + 4 * list;
 }

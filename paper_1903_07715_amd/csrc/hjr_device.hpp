@@ -308,6 +308,29 @@ __device__ __forceinline__ void weno5_pair(const T *d, T eps0, T &dm, T &dp)
     dp = weno5_right(wr, d[1], d[2], d[3], d[4], d[5]);
 }
 
+// The Lax-Friedrichs operator's dissipation sum_d alpha_d (D+ - D-)_d / 2 added to the Hamiltonian
+// term, and the integrator's stage value from the stage input s, the step-start value vn and the
+// operator L (forward Euler, or stage 1, 2, 3 of TVD-RK3 with the discount gm on the step's last
+// stage).  The fused multiply-adds are written out, so the rounding is fixed by the source and
+// every stage kernel (flat tiles, plane march, brick, WENO5 march) produces the same bits.
+template <typename T, int N>
+__device__ __forceinline__ T add_dissipation(T L, const T *alpha, const T *diff)
+{
+#pragma unroll
+    for (int d = 0; d < N; ++d) L = fma(alpha[d], diff[d], L);
+    return L;
+}
+template <typename T>
+__device__ __forceinline__ T stage_value(bool euler, int stage, T gm, T s, T vn, T dt, T L)
+{
+#pragma clang fp contract(off)
+    const T e = fma(dt, L, s);
+    if (euler) return gm * e;
+    if (stage == 0) return e;
+    if (stage == 1) return fma(T(0.75), vn, T(0.25) * e);
+    return gm * fma(vn, T(1.0 / 3.0), T(2.0 / 3.0) * e);
+}
+
 // Every lane of a block works on one tile of one instance, so the instance's array pointers are
 // wave-uniform.  Saying so (readfirstlane of both halves) puts them in scalar registers, and
 // each stencil load then becomes a scalar base plus one shared per-lane byte offset instead of
@@ -578,8 +601,7 @@ __device__ __forceinline__ T lf_operator(const Inst &I, const T *__restrict__ S,
     }
     const T sgn = I.game == 0 ? T(1) : T(-1);
     T L = hamiltonian<T, DYN>(I, uniform_ptr(F::tab(I)), idx, p, alpha, sgn);
-#pragma unroll
-    for (int d = 0; d < N; ++d) L += alpha[d] * diff[d];
+    L = add_dissipation<T, N>(L, alpha, diff);
     *centre = c;
     return L;
 }

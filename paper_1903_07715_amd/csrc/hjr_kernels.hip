@@ -176,17 +176,8 @@ __device__ __forceinline__ void stage_tile(const Inst &I, uint32_t start, int st
         T s;
         T L = lf_operator<T, DYN, SPATIAL>(I, S, node, &s);
         T vn = ldg(Vn, node);
-        T out;
-        if (euler) {
-            out = gm * (s + dt * L);
-            if (!I.brs) out = fmin(ldg(l, node), out);
-            if (G) out = fmax(ldg(G, node), out);
-        } else if (stage == 0) {
-            out = s + dt * L;
-        } else if (stage == 1) {
-            out = T(0.75) * vn + T(0.25) * (s + dt * L);
-        } else {
-            out = gm * (vn * T(1.0 / 3.0) + T(2.0 / 3.0) * (s + dt * L));
+        T out = stage_value<T>(euler, stage, gm, s, vn, dt, L);
+        if (last) {
             if (!I.brs) out = fmin(ldg(l, node), out);
             if (G) out = fmax(ldg(G, node), out);
         }
@@ -376,23 +367,10 @@ template <typename T, int DYN, bool EP> struct MarchUpdate {
             p[d] = h * (dm + dq);
             diff[d] = h * (dq - dm);
         }
-        T L = ham_eval<T, DYN>(I, kc, p, alpha, sgn);
-#pragma unroll
-        for (int d = 0; d < N; ++d) L += alpha[d] * diff[d];
-        const T s = u0;
-        T out;
-        if (EP) {
-            out = fmin(lv, gm * (s + dt * L));
-        } else if (euler) {
-            out = gm * (s + dt * L);
-            if (!I.brs) out = fmin(lv, out);
-            if (hasg) out = fmax(gv, out);
-        } else if (stage == 0) {
-            out = s + dt * L;
-        } else if (stage == 1) {
-            out = T(0.75) * vn + T(0.25) * (s + dt * L);
-        } else {
-            out = gm * (vn * T(1.0 / 3.0) + T(2.0 / 3.0) * (s + dt * L));
+        const T L = add_dissipation<T, N>(ham_eval<T, DYN>(I, kc, p, alpha, sgn), alpha, diff);
+        if (EP) return fmin(lv, stage_value<T>(true, 0, gm, u0, vn, dt, L));
+        T out = stage_value<T>(euler, stage, gm, u0, vn, dt, L);
+        if (euler || stage == 2) {
             if (!I.brs) out = fmin(lv, out);
             if (hasg) out = fmax(gv, out);
         }
@@ -924,22 +902,10 @@ __device__ __forceinline__ void march_tile_w5(const Inst &I, const MTile &tl, in
                 p[d] = h * (dm + dq);
                 diff[d] = h * (dq - dm);
             }
-            T L = ham_eval<T, DYN>(I, kc, p, alpha, sgn);
-#pragma unroll
-            for (int d = 0; d < N; ++d) L += alpha[d] * diff[d];
-            const T s = u0;
+            const T L = add_dissipation<T, N>(ham_eval<T, DYN>(I, kc, p, alpha, sgn), alpha, diff);
             const T vn = euler ? u0 : cur.vn;
-            T out;
-            if (euler) {
-                out = gm * (s + dt * L);
-                if (!I.brs) out = fmin(cur.lv, out);
-                if (G) out = fmax(cur.gv, out);
-            } else if (stage == 0) {
-                out = s + dt * L;
-            } else if (stage == 1) {
-                out = T(0.75) * vn + T(0.25) * (s + dt * L);
-            } else {
-                out = gm * (vn * T(1.0 / 3.0) + T(2.0 / 3.0) * (s + dt * L));
+            T out = stage_value<T>(euler, stage, gm, u0, vn, dt, L);
+            if (last) {
                 if (!I.brs) out = fmin(cur.lv, out);
                 if (G) out = fmax(cur.gv, out);
             }
