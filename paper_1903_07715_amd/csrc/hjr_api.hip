@@ -947,7 +947,11 @@ public:
                 float ms = 0.f;
                 HJR_HIP(hipEventElapsedTime(&ms, e.a, e.b));
                 if (e.group >= 0) {
-                    tuned[{e.prec, e.group}].push_back(ms);
+                    // only launches of steps every instance of the group was taking: after an
+                    // instance finishes, its tiles return at once and the launch says nothing
+                    // about the candidate
+                    auto &v = tuned[{e.prec, e.group}];
+                    if (launch_full(e)) v.push_back(ms);
                     continue;
                 }
                 hjr_kernel_time &kt = e.prec ? g_profile.stage64[e.stage] : g_profile.stage32[e.stage];
@@ -959,17 +963,18 @@ public:
                     kt.working_ms += ms;
                 }
             }
-            // the median launch of the chunk (launches after an instance has finished return
-            // at once and would drag a mean down)
+            // the median of the chunk's full launches; a chunk in which one of the group's
+            // instances changed phase is not used (its launches before or after the change
+            // returned at once).  A chunk in which an instance finished still counts: a solve's
+            // few FP64 polish steps often end inside their first chunk.
             for (auto &kv : tuned) {
                 auto &v = kv.second;
                 std::sort(v.begin(), v.end());
                 const Seg &sg = segs_[kv.first.first][kv.first.second];
-                // a chunk in which one of the group's instances finished (or changed phase) ran
-                // launches that return at once; its timing says nothing about the candidate
-                bool running = true;
-                for (int i : sg.slots) running = running && h_states_[i].done == kRunning;
-                if (running && v.size() >= 3) {
+                bool same_phase = true;
+                for (int i : sg.slots)
+                    same_phase = same_phase && i < (int)before_.size() && h_states_[i].phase == before_[i].phase;
+                if (same_phase && v.size() >= 3) {
                     Tuner::get().record(sg.tune_key, sg.npt, 1e3 * v[v.size() / 2]);
                     if (getenv("HJR_TUNE_VERBOSE"))
                         fprintf(stderr, "[hjr tune] %s npt=%d launches=%zu min=%.1fus median=%.1fus max=%.1fus\n",
@@ -1147,6 +1152,14 @@ private:
     }
     // Whether some instance of the launch's group (every instance, for the fused kernel) was
     // still taking the launch's step.
+    // Whether every instance of the launch's group was still taking the launch's step.
+    bool launch_full(const EvRec &e) const
+    {
+        if (e.seg < 0) return false;
+        for (int i : segs_[e.prec][e.seg].slots)
+            if (i >= (int)before_.size() || steps_taken(i) <= e.step) return false;
+        return true;
+    }
     bool launch_worked(const EvRec &e) const
     {
         if (e.seg < 0) {

@@ -39,12 +39,13 @@ def _field(grid, l, seed):
     return V
 
 
-@pytest.mark.parametrize("npt", ["1", "2", "4", "8", "-1", "-8"])
+@pytest.mark.parametrize("npt", ["1", "2", "4", "8", "-1", "-8", "-16"])
 @pytest.mark.parametrize("name", ["dubins101", "unicycle61", "quad25", "quad25-weno"])
 def test_fullsize_fp32_stages_on_sampled_nodes(gpu, hjrlib, orc, name, npt, monkeypatch):
     """Every launch configuration the autotuner may pick is checked: flat tiles with 1, 2, 4 or 8
-    nodes per thread, and for the upwind quadrotor the plane-march kernel over whole dim-0 lines
-    (-1) and in runs of 8 planes (-8); WENO5 problems fall back to flat tiles for -1/-8."""
+    nodes per thread, the plane-march kernels over whole dim-0 lines (-1) and in runs of 8 planes
+    (-8), and for the upwind quadrotor the brick variant (-16; the other problems run the
+    whole-line march kernel for it)."""
     monkeypatch.setenv("HJR_NPT", npt)
     torch = __import__("torch")
     if name == "dubins101":
