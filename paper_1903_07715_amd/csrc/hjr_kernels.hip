@@ -544,9 +544,9 @@ __global__ __launch_bounds__(kBlock) void march_kernel(const Inst *__restrict__ 
 // bit for bit.  A dim of odd length leaves its last row without a partner; that row loads both
 // of its neighbours from memory (one load: without a partner the row is the dim's last, so a
 // non-periodic end replaces the missing neighbour by the loaded one; the host does not give
-// this kernel a periodic dim of odd length among dims 1..3).  Lanes past the end of a segment,
-// and the rows past the end of a dim, do the loads of the brick's first column and store
-// nothing.
+// this kernel a periodic dim of odd length among dims 1..3).  Lanes past the end of a segment
+// work on the segment's last column and rows past the end of a dim on the brick's first column;
+// neither stores, and every lane passes every barrier.
 // --------------------------------------------------------------------------------------------
 constexpr int kBrickSeg = 128;                          // columns per row segment
 constexpr int kBrickRows = 8;                           // 2 x 2 x 2 rows over dims 1..3
@@ -635,6 +635,7 @@ __device__ __forceinline__ void march_brick_tile(const Inst &I, const MTile &tl,
         bool m = false, p = false;
         T a = T(1), b = T(1);
         if (!rowok) {
+            // a row past a dim's end: its values are never used
         } else if (e[d]) {  // the partner is j - 1
             m = true;
             if (j + 1 < n) q = 1;
