@@ -46,7 +46,7 @@ PEAK_HBM_GBS = 8000.0
 # quadrotor) between L2 and memory, from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a
 # 1 GiB copy calibration (profiles/quad6_25_headline_hbm_counters.txt), keyed by a hash of the
 # kernel sources they were taken from: a kernel changed since then reports null.
-MEASURED_TRAFFIC = {"bb8709c6006f679c": {"quad6": 4.091e9 + 1.007e9}}
+MEASURED_TRAFFIC = {"22dc968893426f53": {"quad6": 4.092e9 + 1.007e9}}
 
 
 def kernel_source_hash() -> str:
