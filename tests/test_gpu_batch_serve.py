@@ -33,6 +33,22 @@ def test_batch_alone_vs_mix_bitwise(gpu, hjrlib):
         assert np.array_equal(V, Va), p.name
 
 
+def test_batch_6d_bricks_alone_vs_mix_bitwise(gpu, hjrlib, monkeypatch):
+    """6-D quadrotors of odd and even grid sizes batched through the brick plane-march kernel
+    (each instance's bricks in one launch) give the results of their solves alone."""
+    monkeypatch.setenv("HJR_NPT", "-16")
+    probs = [W.quad6_problem(9, dbar=(0.5, 0.5, 0.5)), W.quad6_problem(10, dbar=(0.4, 0.3, 0.5)),
+             W.quad6_problem(9, m=1.1, dbar=(0.3, 0.3, 0.3))]
+    opts = [hjrlib.problem_options(p, max_iter=20000) for p in probs]
+    Vs, rs, sts = hjrlib.batch_solve([(p.grid, p.dyn) for p in probs], [p.l for p in probs], [None] * len(probs), opts)
+    for p, o, V, r, st in zip(probs, opts, Vs, rs, sts):
+        Va, ra, sta = hjrlib.solve(p.grid, p.dyn, p.l, None, **o)
+        print(f"[batch] {p.grid.n}: {r['iterations']}+{r['polish_iterations']} steps, status {st}", flush=True)
+        assert st == sta == hjrlib.OK
+        assert (r["iterations"], r["polish_iterations"]) == (ra["iterations"], ra["polish_iterations"])
+        assert np.array_equal(V, Va)
+
+
 def test_batch_matches_oracle(gpu, hjrlib, orc):
     probs = _mix()[1:5]
     Vs, rs, sts = hjrlib.batch_solve([(p.grid, p.dyn) for p in probs], [p.l for p in probs], [None] * len(probs),

@@ -50,6 +50,13 @@ def test_noalloc_matches_solve_device_twice_then_smaller(gpu, hjrlib):
     _pair(hjrlib, gpu, di, precision=hjrlib.FP64, stream=s)             # FP64 upwind on a caller stream
 
 
+def test_noalloc_6d_bricks(gpu, hjrlib, monkeypatch):
+    """A 6-D quadrotor through the brick plane-march kernel, whose tile list the scratch block
+    also has to hold."""
+    monkeypatch.setenv("HJR_NPT", "-16")
+    _pair(hjrlib, gpu, W.quad6_problem(9), precision=hjrlib.FP32_POLISH64)   # 531 441 nodes
+
+
 def test_noalloc_refuses_a_grid_beyond_its_block(gpu, hjrlib):
     import torch
 
